@@ -1,0 +1,228 @@
+"""FP64 CPU oracle for the Euler-step hot path.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+leg of the benchmark may use it; the product path never does.  It shares no
+code with the HIP path.
+
+`euler_oracle.c` holds the arithmetic (plain serial FP64 loops);
+this module is a ctypes wrapper over numpy arrays.  State arrays are numpy
+float64 arrays of shape (d+2, *reversed(n)) — i.e. (d+2, nz, ny, nx) in 3D,
+x fastest — holding rho, m_0..m_{d-1}, E.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "euler_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+PERIODIC = 0
+OUTFLOW = 1
+
+OK = 0
+BAD_ARG = -1
+NONFINITE = -4
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
+                ("gamma", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
+                ("pad2_", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        mp = ctypes.POINTER(_Mesh)
+        lib.orc_stage.argtypes = [mp, dp, dp, ctypes.c_double, dp]
+        lib.orc_step.argtypes = [mp, dp, ctypes.c_double, dp]
+        lib.orc_cfl_qmax.argtypes = [mp, dp, dp]
+        lib.orc_cfl_dt.argtypes = [mp, dp, ctypes.c_double, dp]
+        lib.orc_totals.argtypes = [mp, dp, dp]
+        lib.orc_advance.argtypes = [mp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                    dp, ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_hllc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        lib.orc_minmod.argtypes = [ctypes.c_double, ctypes.c_double]
+        lib.orc_minmod.restype = ctypes.c_double
+        lib.orc_interpolate.argtypes = [ctypes.c_double] * 3 + [dp, dp]
+        lib.orc_prim_of_cons.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        lib.orc_cons_of_prim.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        for fn in ("orc_stage", "orc_step", "orc_cfl_qmax", "orc_cfl_dt", "orc_totals",
+                   "orc_advance"):
+            getattr(lib, fn).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Mesh:
+    """Uniform mesh on [0,1]^d (or the given spacings), n = (nx, ny, nz)."""
+    ndim: int
+    n: tuple
+    gamma: float
+    bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    dx: tuple | None = None
+    _c: _Mesh = field(init=False, repr=False)
+
+    def __post_init__(self):
+        n = tuple(int(v) for v in self.n) + (1,) * (3 - len(self.n))
+        self.n = n
+        if self.dx is None:
+            self.dx = tuple(1.0 / n[a] if a < self.ndim else 1.0 for a in range(3))
+        else:
+            self.dx = tuple(float(v) for v in self.dx) + (1.0,) * (3 - len(self.dx))
+        bc = tuple(int(b) for b in self.bc) + (PERIODIC,) * (3 - len(self.bc))
+        self.bc = bc
+        c = _Mesh()
+        c.ndim = self.ndim
+        for a in range(3):
+            c.n[a] = n[a]
+            c.dx[a] = self.dx[a]
+            c.bc[a] = bc[a]
+        c.gamma = float(self.gamma)
+        self._c = c
+
+    @property
+    def nf(self) -> int:
+        return self.ndim + 2
+
+    @property
+    def shape(self) -> tuple:
+        return (self.nf,) + tuple(reversed(self.n[: self.ndim]))
+
+    @property
+    def ncells(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _as_state(mesh: Mesh, U) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.size != mesh.nf * mesh.ncells:
+        raise OracleError(f"state has {U.size} values, mesh needs {mesh.nf * mesh.ncells}")
+    return U.reshape(mesh.shape)
+
+
+def _check(rc: int, what: str):
+    if rc == NONFINITE:
+        raise FloatingPointError(f"{what}: non-physical or non-finite state")
+    if rc != OK:
+        raise OracleError(f"{what}: status {rc}")
+
+
+def stage(mesh: Mesh, U_in, U_base, cdt: float) -> np.ndarray:
+    lib = _load()
+    a, b = _as_state(mesh, U_in), _as_state(mesh, U_base)
+    out = np.empty_like(a)
+    _check(lib.orc_stage(ctypes.byref(mesh._c), _ptr(a), _ptr(b), float(cdt), _ptr(out)), "stage")
+    return out
+
+
+def step(mesh: Mesh, U0, dt: float) -> np.ndarray:
+    """One midpoint-RK2 step with the given dt (FP64)."""
+    lib = _load()
+    a = _as_state(mesh, U0)
+    out = np.empty_like(a)
+    _check(lib.orc_step(ctypes.byref(mesh._c), _ptr(a), float(dt), _ptr(out)), "step")
+    return out
+
+
+def cfl_qmax(mesh: Mesh, U) -> float:
+    lib = _load()
+    a = _as_state(mesh, U)
+    q = ctypes.c_double()
+    _check(lib.orc_cfl_qmax(ctypes.byref(mesh._c), _ptr(a), ctypes.byref(q)), "cfl")
+    return q.value
+
+
+def cfl_dt(mesh: Mesh, U, cfl: float) -> float:
+    lib = _load()
+    a = _as_state(mesh, U)
+    dt = ctypes.c_double()
+    _check(lib.orc_cfl_dt(ctypes.byref(mesh._c), _ptr(a), float(cfl), ctypes.byref(dt)), "cfl")
+    return dt.value
+
+
+def totals(mesh: Mesh, U) -> np.ndarray:
+    lib = _load()
+    a = _as_state(mesh, U)
+    out = np.zeros(mesh.nf)
+    _check(lib.orc_totals(ctypes.byref(mesh._c), _ptr(a), _ptr(out)), "totals")
+    return out
+
+
+def advance(mesh: Mesh, U0, cfl: float, t_end: float, max_steps: int = 1 << 40, t0: float = 0.0):
+    """Advance a copy of U0 to t_end; returns (U, t, steps)."""
+    lib = _load()
+    U = _as_state(mesh, U0).copy()
+    t = ctypes.c_double(t0)
+    steps = ctypes.c_int64()
+    _check(lib.orc_advance(ctypes.byref(mesh._c), _ptr(U), float(cfl), float(t_end),
+                           int(max_steps), ctypes.byref(t), ctypes.byref(steps)), "advance")
+    return U, t.value, steps.value
+
+
+# ---- single-cell pieces, exposed for the unit pins -----------------------------------
+
+def minmod(a: float, b: float) -> float:
+    return _load().orc_minmod(float(a), float(b))
+
+
+def interpolate(y0: float, y1: float, y2: float) -> tuple[float, float]:
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _load().orc_interpolate(float(y0), float(y1), float(y2), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def hllc(ndim: int, gamma: float, axis: int, vl, vr) -> np.ndarray:
+    lib = _load()
+    vl = np.ascontiguousarray(vl, dtype=np.float64)
+    vr = np.ascontiguousarray(vr, dtype=np.float64)
+    f = np.zeros(ndim + 2)
+    lib.orc_hllc(int(ndim), float(gamma), int(axis), _ptr(vl), _ptr(vr), _ptr(f))
+    return f
+
+
+def prim_of_cons(ndim: int, gamma: float, u) -> np.ndarray:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    v = np.zeros(ndim + 2)
+    _load().orc_prim_of_cons(int(ndim), float(gamma), _ptr(u), _ptr(v))
+    return v
+
+
+def cons_of_prim(ndim: int, gamma: float, v) -> np.ndarray:
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    u = np.zeros(ndim + 2)
+    _load().orc_cons_of_prim(int(ndim), float(gamma), _ptr(v), _ptr(u))
+    return u

@@ -1,0 +1,401 @@
+"""Pins of the FP64 CPU oracle to facts fixed outside it.
+
+Each test names what fixes the expected value: a textbook table, a hand
+derivation from the paper's equations, an exact property of the scheme
+(telescoping flux sums, symmetry, consistency), or a convergence rate.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact_riemann as er
+from paper_1204_4779_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _mesh(pr):
+    return oracle.Mesh(pr.ndim, pr.n, pr.gamma, pr.bc)
+
+
+# --------------------------------------------------------------------------------------
+# single-cell pieces
+# --------------------------------------------------------------------------------------
+
+def test_minmod_truth_table():
+    # Interpolate equation: 0 on opposite signs, the smaller-magnitude slope otherwise,
+    # dy12 on a tie.
+    cases = [((1.0, 2.0), 1.0), ((2.0, 1.0), 1.0), ((-1.0, -2.0), -1.0), ((-3.0, -0.5), -0.5),
+             ((1.0, -1.0), 0.0), ((-2.0, 1.0), 0.0), ((0.0, 5.0), 0.0), ((5.0, 0.0), 0.0),
+             ((3.0, 3.0), 3.0), ((-4.0, -4.0), -4.0), ((1e-300, 1e-300), 1e-300)]
+    for (a, b), want in cases:
+        assert oracle.minmod(a, b) == want, (a, b)
+
+
+def test_minmod_odd_symmetry():
+    # Mirroring a profile maps (dy01, dy12) -> (-dy12, -dy01); the limited slope must flip.
+    rng = np.random.default_rng(3)
+    vals = np.concatenate([rng.normal(size=400), [0.0, 1.0, -1.0, 2.0]])
+    for a, b in zip(vals[:-1], vals[1:]):
+        assert oracle.minmod(-b, -a) == -oracle.minmod(a, b)
+    assert oracle.minmod(-1.5, -1.5) == -oracle.minmod(1.5, 1.5)
+
+
+def test_interpolate_values():
+    lo, hi = oracle.interpolate(1.0, 2.0, 4.0)   # slopes 1, 2 -> dy = 1
+    assert (lo, hi) == (1.5, 2.5)
+    lo, hi = oracle.interpolate(1.0, 3.0, 2.0)   # extremum -> dy = 0
+    assert (lo, hi) == (3.0, 3.0)
+
+
+def test_prim_cons_hand_values():
+    g = _golden("hand_values.json")
+    st = g["state_2d"]
+    u = oracle.cons_of_prim(2, st["gamma"], st["prim"])
+    # gamma - 1 = 0.4 is not exact in binary: E agrees to rounding
+    np.testing.assert_allclose(u, st["cons"], rtol=4 * np.finfo(float).eps)
+    v = oracle.prim_of_cons(2, st["gamma"], st["cons"])
+    np.testing.assert_allclose(v, st["prim"], rtol=4 * np.finfo(float).eps)
+
+
+def test_prim_cons_round_trip_ulps():
+    rng = np.random.default_rng(7)
+    for ndim in (1, 2, 3):
+        for _ in range(200):
+            v = np.concatenate([[rng.uniform(0.1, 10)], rng.uniform(-3, 3, ndim),
+                                [rng.uniform(0.1, 10)]])
+            gamma = rng.choice([1.4, 5.0 / 3.0, 1.1])
+            back = oracle.prim_of_cons(ndim, gamma, oracle.cons_of_prim(ndim, gamma, v))
+            u = oracle.cons_of_prim(ndim, gamma, v)
+            back_u = oracle.cons_of_prim(ndim, gamma, oracle.prim_of_cons(ndim, gamma, u))
+            np.testing.assert_allclose(back_u, u, rtol=8 * np.finfo(float).eps, atol=1e-15)
+            # rho and velocities exactly-ish; pressure loses digits when kinetic >> internal
+            np.testing.assert_allclose(back[: ndim + 1], v[: ndim + 1], rtol=4 * np.finfo(float).eps)
+
+
+def test_hllc_hand_values():
+    g = _golden("hand_values.json")
+    v = np.array(g["state_2d"]["prim"])
+    fx = oracle.hllc(2, 1.4, 0, v, v)
+    np.testing.assert_array_equal(fx, oracle.hllc(2, 1.4, 0, v, v * [1, 1, 1, 1]))
+    np.testing.assert_allclose(fx, g["flux_x"]["value"], rtol=4 * np.finfo(float).eps)
+    fy = oracle.hllc(2, 1.4, 1, v, v)
+    np.testing.assert_allclose(fy, g["flux_y"]["value"], rtol=1e-14, atol=1e-14)
+
+
+def test_hllc_stationary_contact_and_shear():
+    # u = 0 on both sides, equal pressure: the exact flux is (0, p, 0, ..., 0) whatever the
+    # density and tangential-velocity jumps.
+    for ndim in (1, 2, 3):
+        vl = np.array([1.0] + [0.0] + [0.3] * (ndim - 1) + [0.7])
+        vr = np.array([0.2] + [0.0] + [-1.1] * (ndim - 1) + [0.7])
+        f = oracle.hllc(ndim, 1.4, 0, vl, vr)
+        want = np.zeros(ndim + 2)
+        want[1] = 0.7
+        np.testing.assert_array_equal(f, want)
+
+
+def test_hllc_moving_contact_is_upwind():
+    # An isolated contact moving with speed u > 0 (equal u and p) is resolved exactly by
+    # HLLC: the flux is the physical flux of the upwind (left) state.
+    gamma, u, p = 1.4, 0.4, 1.3
+    vl = np.array([3.0, u, 0.2, p])
+    vr = np.array([0.5, u, -0.6, p])
+    f = oracle.hllc(2, gamma, 0, vl, vr)
+    rho, vt = vl[0], vl[2]
+    E = p / (gamma - 1) + 0.5 * rho * (u * u + vt * vt)
+    np.testing.assert_allclose(f, [rho * u, rho * u * u + p, rho * u * vt, u * (E + p)], rtol=1e-14)
+
+
+def test_hllc_supersonic_upwinding_exact():
+    gamma = 1.4
+    vl = np.array([1.0, 5.0, 1.0])
+    vr = np.array([0.3, 4.0, 0.2])
+    f_lr = oracle.hllc(1, gamma, 0, vl, vr)
+    f_ll = oracle.hllc(1, gamma, 0, vl, vl)
+    np.testing.assert_array_equal(f_lr, f_ll)        # S_L >= 0: left flux, bit for bit
+    vl2, vr2 = vl * [1, -1, 1], vr * [1, -1, 1]
+    f_rl = oracle.hllc(1, gamma, 0, vr2, vl2)         # S_R <= 0: right flux
+    f_rr = oracle.hllc(1, gamma, 0, vl2, vl2)
+    np.testing.assert_array_equal(f_rl, f_rr)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_hllc_weak_waves_match_godunov_to_second_order(ndim):
+    # For jumps of size eps, any consistent approximate solver with correct wave speeds
+    # differs from the exact (Godunov) flux by O(eps^2).  A dropped or mis-signed term in
+    # the star state shows up as an O(eps) difference.  Exact flux from the exact solver.
+    gamma = 1.4
+    rng = np.random.default_rng(11 + ndim)
+    base = np.array([1.2, 0.25] + [0.1] * (ndim - 1) + [0.9])
+    direction = rng.normal(size=ndim + 2)
+    ratios = []
+    for eps in (1e-2, 1e-3, 1e-4):
+        vl = base.copy()
+        vr = base + eps * direction
+        f = oracle.hllc(ndim, gamma, 0, vl, vr)
+        r, un, p = er.sample(gamma, er.Side(vl[0], vl[1], vl[-1]), er.Side(vr[0], vr[1], vr[-1]), 0.0)
+        # tangential velocity is advected with the contact: upwind side by sign of u*
+        ps, us = er.star_state(gamma, er.Side(vl[0], vl[1], vl[-1]), er.Side(vr[0], vr[1], vr[-1]))
+        vt = vl[2:-1] if us >= 0 else vr[2:-1]
+        E = p / (gamma - 1) + 0.5 * r * (un * un + float(np.dot(vt, vt)))
+        fe = np.concatenate([[r * un, r * un * un + p], r * un * vt, [un * (E + p)]])
+        ratios.append(np.max(np.abs(f - fe)) / eps ** 2)
+    assert max(ratios) < 10.0
+    assert ratios[-1] < 2.0 * ratios[0] + 1e-3
+
+
+def test_hllc_axis_permutation():
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        vl = np.array([rng.uniform(0.2, 2), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.2, 2)])
+        vr = np.array([rng.uniform(0.2, 2), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.2, 2)])
+        fx = oracle.hllc(2, 1.4, 0, vl, vr)
+        fy = oracle.hllc(2, 1.4, 1, vl[[0, 2, 1, 3]], vr[[0, 2, 1, 3]])
+        np.testing.assert_allclose(fy[[0, 2, 1, 3]], fx, rtol=1e-14, atol=1e-14)
+
+
+# --------------------------------------------------------------------------------------
+# exact Riemann solver (scores the shock tube)
+# --------------------------------------------------------------------------------------
+
+def test_exact_riemann_sod_star_matches_textbook():
+    g = _golden("sod_star_toro.json")
+    L, R = er.Side(*g["left"]), er.Side(*g["right"])
+    w = er.waves(g["gamma"], L, R)
+    assert abs(w.p_star - g["p_star"]) < 1e-5
+    assert abs(w.u_star - g["u_star"]) < 1e-5
+    assert abs(w.rho_star_l - g["rho_star_left"]) < 1e-5
+    assert abs(w.rho_star_r - g["rho_star_right"]) < 1e-5
+
+
+def test_exact_riemann_shock_satisfies_rankine_hugoniot():
+    gamma = 1.4
+    L, R = er.Side(1.0, 0.0, 1.0), er.Side(0.125, 0.0, 0.1)
+    w = er.waves(gamma, L, R)
+    s = w.right_head
+    # across the right shock: s [U] = [F]
+    def cons(r, u, p):
+        return np.array([r, r * u, p / (gamma - 1) + 0.5 * r * u * u])
+
+    def flux(r, u, p):
+        E = p / (gamma - 1) + 0.5 * r * u * u
+        return np.array([r * u, r * u * u + p, u * (E + p)])
+    ul, ur = cons(w.rho_star_r, w.u_star, w.p_star), cons(R.rho, R.u, R.p)
+    fl, fr = flux(w.rho_star_r, w.u_star, w.p_star), flux(R.rho, R.u, R.p)
+    np.testing.assert_allclose(s * (ur - ul), fr - fl, rtol=1e-12, atol=1e-12)
+    # across the rarefaction: isentropic, Riemann invariant u + 2c/(gamma-1) conserved
+    cL = math.sqrt(gamma * L.p / L.rho)
+    cs = math.sqrt(gamma * w.p_star / w.rho_star_l)
+    assert abs((L.u + 2 * cL / (gamma - 1)) - (w.u_star + 2 * cs / (gamma - 1))) < 1e-12
+    assert abs(L.p / L.rho ** gamma - w.p_star / w.rho_star_l ** gamma) < 1e-12
+
+
+# --------------------------------------------------------------------------------------
+# whole scheme
+# --------------------------------------------------------------------------------------
+
+def _sod_exact_rho(n, t):
+    x = inputs.centres(n)
+    ex = er.sample_cells(1.4, er.Side(1, 0, 1), er.Side(0.125, 0, 0.1), 0.5, t, x)
+    return np.array([e[0] for e in ex]), np.array([e[1] for e in ex]), np.array([e[2] for e in ex])
+
+
+def test_sod_1024_against_exact_solution():
+    pr = inputs.sod_1d(1024)
+    m = _mesh(pr)
+    U, t, steps = oracle.advance(m, pr.U, 0.5, 0.2)
+    assert t == 0.2 and 850 < steps < 950
+    rho_ex, u_ex, p_ex = _sod_exact_rho(1024, 0.2)
+    l1 = np.mean(np.abs(U[0] - rho_ex))
+    assert l1 < 5e-3
+    V = np.array([oracle.prim_of_cons(1, 1.4, U[:, i]) for i in range(1024)]).T
+    x = inputs.centres(1024)
+    plateau = (x > 0.72) & (x < 0.82)
+    w = er.waves(1.4, er.Side(1, 0, 1), er.Side(0.125, 0, 0.1))
+    np.testing.assert_allclose(V[2][plateau], w.p_star, rtol=1e-3)
+    np.testing.assert_allclose(V[1][plateau], w.u_star, rtol=1e-3)
+
+
+@pytest.mark.slow
+def test_sod_convergence_first_order():
+    errs = []
+    ns = (256, 512, 1024, 2048)
+    for n in ns:
+        pr = inputs.sod_1d(n)
+        U, t, _ = oracle.advance(_mesh(pr), pr.U, 0.5, 0.2)
+        errs.append(np.mean(np.abs(U[0] - _sod_exact_rho(n, 0.2)[0])))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(0.6 < o < 1.3 for o in orders), orders
+
+
+@pytest.mark.parametrize("ndim,n", [(1, (16,)), (2, (12, 7)), (3, (6, 5, 4))])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_uniform_flow_is_bitwise_steady(ndim, n, bc):
+    pr = inputs.uniform_flow(ndim, n, bc=(bc,) * 3)
+    m = _mesh(pr)
+    U2 = oracle.step(m, pr.U, 3e-3)
+    np.testing.assert_array_equal(U2, pr.U)
+
+
+@pytest.mark.parametrize("ndim,n", [(1, (64,)), (2, (24, 16)), (3, (10, 8, 6))])
+def test_periodic_conservation(ndim, n):
+    pr = inputs.random_state(ndim, n, seed=21, rough=True)
+    m = _mesh(pr)
+    dt = oracle.cfl_dt(m, pr.U, 0.5)
+    U2 = oracle.step(m, pr.U, dt)
+    a, b = oracle.totals(m, pr.U), oracle.totals(m, U2)
+    scale = oracle.totals(m, np.abs(pr.U))
+    assert np.all(np.abs(b - a) <= 1e-13 * scale)
+    assert np.max(np.abs(U2 - pr.U)) > 1e-3       # the state did evolve
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_mirror_symmetry_1d(bc):
+    pr = inputs.random_state(1, (40,), seed=5, rough=True, bc=(bc,))
+    m = _mesh(pr)
+    mirror = pr.U[:, ::-1].copy()
+    mirror[1] *= -1.0
+    dt = 2e-3
+    a = oracle.step(m, pr.U, dt)
+    b = oracle.step(m, mirror, dt)
+    b = b[:, ::-1].copy()
+    b[1] *= -1.0
+    np.testing.assert_allclose(b, a, rtol=1e-13, atol=1e-13 * np.max(np.abs(a)))
+
+
+def test_axis_permutation_2d():
+    pr = inputs.random_state(2, (12, 9), seed=8, rough=True)
+    m = _mesh(pr)
+    swapped = pr.U.transpose(0, 2, 1)[[0, 2, 1, 3]].copy()     # x <-> y
+    ms = oracle.Mesh(2, (9, 12), 1.4, (0, 0))
+    dt = 1e-3
+    a = oracle.step(m, pr.U, dt)
+    b = oracle.step(ms, swapped, dt)
+    b = b[[0, 2, 1, 3]].transpose(0, 2, 1)
+    np.testing.assert_allclose(b, a, rtol=1e-13, atol=1e-13 * np.max(np.abs(a)))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_1d_embedded_in_higher_dimension(ndim, bc):
+    pr1 = inputs.random_state(1, (24,), seed=9, rough=True, bc=(bc,))
+    m1 = _mesh(pr1)
+    dt = 1.5e-3
+    ref = oracle.step(m1, pr1.U, dt)
+    shape = (4,) * (ndim - 1) + (24,) if ndim == 2 else (3, 4, 24)
+    n = (24, 4, 3)[:ndim]
+    U = np.zeros((ndim + 2,) + shape)
+    U[0] = pr1.U[0]
+    U[1] = pr1.U[1]
+    U[ndim + 1] = pr1.U[2]
+    m = oracle.Mesh(ndim, n, 1.4, (bc,) * 3)
+    out = oracle.step(m, U, dt)
+    for k in range(1, ndim):
+        assert np.all(out[1 + k] == 0.0)
+    # identical to the 1D run up to rounding (transverse fluxes cancel exactly)
+    np.testing.assert_allclose(out[0].reshape(-1, 24), np.broadcast_to(ref[0], (out[0].size // 24, 24)),
+                               rtol=1e-14)
+    np.testing.assert_allclose(out[ndim + 1].reshape(-1, 24),
+                               np.broadcast_to(ref[2], (out[0].size // 24, 24)), rtol=1e-14)
+
+
+def test_cfl_uniform_closed_form():
+    g = _golden("hand_values.json")
+    c = g["cfl_uniform_2d"]
+    st = g["state_2d"]
+    n = c["n"]
+    U = np.empty((4, n[1], n[0]))
+    for q in range(4):
+        U[q] = st["cons"][q]
+    m = oracle.Mesh(2, tuple(n), 1.4, (0, 0))
+    dt = oracle.cfl_dt(m, U, c["cfl"])
+    assert abs(dt - float(c["value"])) <= 4e-16 * dt
+
+
+def test_cfl_flags_nonphysical_state():
+    pr = inputs.random_state(2, (8, 8), seed=2)
+    m = _mesh(pr)
+    bad = pr.U.copy()
+    bad[0, 3, 4] = -1.0
+    with pytest.raises(FloatingPointError):
+        oracle.cfl_dt(m, bad, 0.5)
+    bad = pr.U.copy()
+    bad[3, 1, 1] = np.nan
+    with pytest.raises(FloatingPointError):
+        oracle.cfl_dt(m, bad, 0.5)
+
+
+def test_midpoint_structure():
+    # Time marching equations: U1 = AddFlux(dt/2, Flux(U0), U0), U2 = AddFlux(dt, Flux(U1), U0).
+    pr = inputs.random_state(2, (10, 8), seed=4)
+    m = _mesh(pr)
+    dt = 2e-3
+    u1 = oracle.stage(m, pr.U, pr.U, 0.5 * dt)
+    u2 = oracle.stage(m, u1, pr.U, dt)
+    np.testing.assert_array_equal(oracle.step(m, pr.U, dt), u2)
+    # Heun's form differs at second order for this nonlinear problem
+    ue = oracle.stage(m, pr.U, pr.U, dt)
+    heun = 0.5 * (pr.U + oracle.stage(m, ue, ue, dt))
+    assert np.max(np.abs(heun - u2)) > 1e-9
+
+
+def _smooth_1d(n):
+    x = inputs.centres(n)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * x)
+    v = 0.3 + 0.1 * np.cos(2 * np.pi * x)
+    p = 1.0 + 0.1 * np.sin(2 * np.pi * x + 1.0)
+    return inputs.conserved(1.4, rho, [v], p)
+
+
+def test_time_order_two():
+    # Fixed mesh, smooth data, several dt: the one-interval error against a tiny-dt run
+    # must fall like dt^2 (a first-order mistake in either stage gives dt^1).
+    n = 64
+    U0 = _smooth_1d(n)
+    m = oracle.Mesh(1, (n,), 1.4, (0,))
+    T = 0.004
+
+    def run(nsteps):
+        U = U0
+        for _ in range(nsteps):
+            U = oracle.step(m, U, T / nsteps)
+        return U
+    ref = run(256)
+    errs = [np.max(np.abs(run(k) - ref)) for k in (2, 4, 8)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(o > 1.8 for o in orders), orders
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", ["entropy", "sound"])
+def test_smooth_wave_convergence(which):
+    errs = []
+    ns = (64, 128, 256)
+    for n in ns:
+        pr = inputs.entropy_wave_1d(n) if which == "entropy" else inputs.sound_wave_1d(n)
+        U, t, _ = oracle.advance(_mesh(pr), pr.U, 0.5, 1.0)
+        assert t == 1.0
+        errs.append(np.mean(np.abs(U[0] - pr.U[0])))     # t = 1 returns to the initial state
+        if which == "entropy":
+            V = np.array([oracle.prim_of_cons(1, 1.4, U[:, i]) for i in range(n)]).T
+            assert np.max(np.abs(V[1] - 1.0)) < 1e-12
+            assert np.max(np.abs(V[2] - 1.0)) < 1e-12
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(o > 1.5 for o in orders), (errs, orders)
+
+
+def test_totals_exact_on_integers():
+    m = oracle.Mesh(2, (4, 2), 1.4, (0, 0))
+    U = np.arange(32, dtype=float).reshape(4, 2, 4)
+    t = oracle.totals(m, U)
+    np.testing.assert_array_equal(t, [28 / 8, 92 / 8, 156 / 8, 220 / 8])
