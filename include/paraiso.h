@@ -1,0 +1,193 @@
+/*
+ * paraiso.h — C ABI of the MI355X (gfx950) explicit Euler-step library.
+ *
+ * The library advances the ideal-gas Euler equations on uniform 1D/2D/3D
+ * meshes with the scheme of Paraiso (arXiv:1204.4779, section "Tuning
+ * Experiments / The Target Program"):
+ *   - primitive V = (rho, v_a, p) and conserved U = (rho, m_a, E) with
+ *     m_a = rho v_a and E = p/(gamma-1) + rho v^2/2 (state-vector equations);
+ *   - minbee (minmod) piecewise-linear reconstruction of V along each axis
+ *     (Interpolate equation);
+ *   - HLLC face fluxes (Toro, Spruce, Speares 1994, as cited there);
+ *   - AddFlux U_out = U_base + sum_a (dt/dr_a)(F_a[i-1/2] - F_a[i+1/2]);
+ *   - the two-stage midpoint time marching
+ *       U1 = AddFlux(dt/2, Flux(U0), U0),  U2 = AddFlux(dt, Flux(U1), U0);
+ *   - dt from the CFL condition, dt = C / max_i sum_a (|v_a| + c)/dr_a with
+ *     c = sqrt(gamma p / rho), taken as a global min-reduction over cells
+ *     (the Orthotope Machine's Reduce Min).
+ *
+ * Memory ownership: the caller allocates every device buffer (state fields
+ * and the workspace), keeps them alive for the lifetime of the context, and
+ * frees them after paraiso_destroy.  The library never allocates or frees
+ * device memory.  It never aborts: every entry point returns a status code
+ * and, on failure, leaves a message for paraiso_last_error().
+ *
+ * Streams: a context is bound to the HIP stream given at init and is not
+ * thread-safe; calls on one context must come from one thread at a time.
+ * Asynchronous calls (paraiso_step) return after enqueueing work on that
+ * stream.  Synchronous calls (cfl_dt, advance, totals) return after the
+ * work they enqueued has finished.
+ *
+ * Layout of a state buffer: d+2 separate device arrays (rho, m_0..m_{d-1},
+ * E), each holding n[0]*n[1]*n[2] reals in x-fastest order:
+ * field[(k*n[1] + j)*n[0] + i].  Element type float (PARAISO_F32) or double
+ * (PARAISO_F64); arrays must be 16-byte aligned.
+ */
+#ifndef PARAISO_H
+#define PARAISO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PARAISO_OK 0
+#define PARAISO_ERR_INVALID_ARG (-1)     /* a pointer, size or value is outside its documented range */
+#define PARAISO_ERR_UNSUPPORTED (-2)     /* valid request that this build cannot run (variant, size) */
+#define PARAISO_ERR_HIP (-3)             /* a HIP runtime call failed; message holds the HIP error */
+#define PARAISO_ERR_NONFINITE (-4)       /* a cell has rho <= 0, p <= 0 or a non-finite value */
+#define PARAISO_ERR_WORKSPACE (-5)       /* workspace smaller than paraiso_workspace_bytes reports */
+
+/* boundary conditions per axis */
+#define PARAISO_PERIODIC 0               /* wrap-around */
+#define PARAISO_OUTFLOW 1                /* zero-gradient: ghost cells copy the edge cell's U */
+
+/* element types */
+#define PARAISO_F32 0
+#define PARAISO_F64 1
+
+/*
+ * One mesh.  n[a] >= 1 cells along axis a (n[a] == 1 for a >= ndim),
+ * dx[a] > 0 the cell size (ignored for a >= ndim), gamma > 1 the ratio of
+ * specific heats.  state[b][q] is field q of buffer b (q < ndim+2), a
+ * device pointer; the two buffers must not overlap.  The library reads the
+ * current state from one buffer and writes the next state to the other
+ * (paraiso_current says which holds the current state).
+ * Limits: n[0]*n[1]*n[2] < 2^31.
+ */
+typedef struct paraiso_mesh {
+  int32_t ndim;
+  int32_t dtype;
+  int64_t n[3];
+  double dx[3];
+  double gamma;
+  int32_t bc[3];
+  int32_t reserved;
+  void* state[2][5];
+} paraiso_mesh;
+
+/*
+ * Kernel variant (the tuning space).  These choices change speed, never
+ * results beyond floating-point rounding.
+ *   tile[a]      cells per workgroup tile along axis a (1 for unused axes);
+ *   lds          1: stage primitive states and face fluxes through LDS, each
+ *                face flux computed once per tile; 0: every cell computes
+ *                its own 2d face fluxes from global memory;
+ *   fuse         1: both Runge-Kutta stages in one launch, stage 1
+ *                recomputed on a halo of 2 cells; 0: one launch per stage,
+ *                stage-1 state kept in the workspace;
+ *   waves_per_eu 0 (compiler's choice), 1, 2 or 4: occupancy hint that
+ *                bounds registers per lane;
+ *   threads      workgroup size, a multiple of 64 in [64, 1024], or 0 for
+ *                the default of the chosen kernel.
+ */
+typedef struct paraiso_variant {
+  int32_t tile[3];
+  int32_t lds;
+  int32_t fuse;
+  int32_t waves_per_eu;
+  int32_t threads;
+  int32_t persistent;  /* 1: grid of a few workgroups per CU pulling tiles from a queue */
+} paraiso_variant;
+
+typedef struct paraiso_ctx paraiso_ctx;
+
+/*
+ * Bytes of device workspace needed for `count` meshes (stage-1 state for
+ * the unfused variants, per-mesh time-stepping control, reduction partials,
+ * mesh table, work queue).  The figure covers every variant, so
+ * paraiso_set_variant never needs a larger workspace.
+ * Errors: INVALID_ARG for a null pointer or an invalid mesh.
+ */
+int32_t paraiso_workspace_bytes(const paraiso_mesh* meshes, int32_t count, size_t* bytes);
+
+/*
+ * Create a context over `count` meshes (count > 1: a batch of independent
+ * meshes that are stepped together; all must share ndim and dtype).
+ * `workspace` is a device buffer of at least paraiso_workspace_bytes bytes,
+ * 256-byte aligned, borrowed for the context's lifetime.  `hip_stream` is a
+ * hipStream_t (NULL = the default stream).  The mesh descriptors are copied;
+ * buffer 0 holds the initial state.
+ * Errors: INVALID_ARG (null pointers, ndim not in 1..3, n < 1, gamma <= 1,
+ * dx <= 0 or non-finite, bc not PERIODIC/OUTFLOW, overlapping buffers,
+ * mixed ndim/dtype in a batch), UNSUPPORTED (too many cells),
+ * WORKSPACE (workspace too small), HIP.
+ */
+int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
+                     size_t workspace_bytes, void* hip_stream, paraiso_ctx** out);
+
+/* Select the kernel variant.  UNSUPPORTED if the variant does not fit the
+ * hardware limits (LDS bytes, threads, registers) or the mesh. */
+int32_t paraiso_set_variant(paraiso_ctx* ctx, const paraiso_variant* v);
+int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
+
+/* The default variant the library picks for these meshes. */
+int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
+
+/*
+ * CFL time step of the current state of every mesh:
+ * dt_out[m] = cfl / max_i sum_a (|v_a| + c)/dx_a, computed in FP64 whatever
+ * the state's element type.  Synchronous.  0 < cfl <= 1.
+ * Errors: INVALID_ARG, NONFINITE (any cell with rho <= 0, p <= 0 or a
+ * non-finite value; dt_out is then unspecified), HIP.
+ */
+int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
+
+/*
+ * One midpoint-RK2 step of every mesh with the caller's time steps
+ * dt[m] >= 0 (finite).  Reads the current buffer, writes the other one and
+ * makes it current.  Asynchronous on the context's stream.
+ * Errors: INVALID_ARG, HIP.
+ */
+int32_t paraiso_step(paraiso_ctx* ctx, const double* dt);
+
+/*
+ * Advance every mesh from t_inout[m] towards t_end with dt = CFL step
+ * clamped so that no step passes t_end, for at most max_steps steps per
+ * mesh.  The time step, the time and the step count stay on the device;
+ * step sequences are replayed from captured HIP graphs.  On return
+ * t_inout[m] and steps_out[m] hold each mesh's time and steps taken.
+ * Synchronous.  0 < cfl <= 1, max_steps >= 0, t_end finite.
+ * Errors: INVALID_ARG, NONFINITE (the state became non-physical; the
+ * state buffers then hold the offending step's output), HIP.
+ */
+int32_t paraiso_advance(paraiso_ctx* ctx, double t_end, double cfl, int64_t max_steps,
+                        double* t_inout, int64_t* steps_out);
+
+/* Index (0 or 1) of the buffer holding the current state. */
+int32_t paraiso_current(const paraiso_ctx* ctx, int32_t* idx);
+
+/*
+ * Conserved totals of the current state: out[m*(ndim+2) + q] = cell volume
+ * times the sum over cells of field q of mesh m, accumulated in FP64 in a
+ * fixed order (bitwise reproducible for a given variant).  Synchronous.
+ */
+int32_t paraiso_totals(paraiso_ctx* ctx, double* out);
+
+/* Release the context (never the caller's buffers).  NULL is a no-op. */
+int32_t paraiso_destroy(paraiso_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* paraiso_last_error(void);
+
+/* Library version string. */
+const char* paraiso_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARAISO_H */

@@ -1,0 +1,229 @@
+// Device-side numerics of the Euler step for gfx950.
+//
+// Scheme (paper, "Tuning Experiments / The Target Program"): conserved
+// U = (rho, m_a, E), primitive V = (rho, v_a, p), minbee piecewise-linear
+// reconstruction of V along each axis, HLLC face fluxes (Toro-Spruce-Speares,
+// cited there), AddFlux with the usual sign of the conservation law, and the
+// two-stage midpoint Runge-Kutta marching.  dt comes from the CFL condition
+// as a global max-reduction of sum_a (|v_a| + c)/dx_a in FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace paraiso {
+
+constexpr int kMaxFields = 5;
+constexpr int kPeriodic = 0;
+constexpr int kOutflow = 1;
+
+// ---------------------------------------------------------------------------
+// integer helpers
+// ---------------------------------------------------------------------------
+
+// Division by a run-time invariant d via a 32x32->hi multiply:
+// q = umulhi(n, floor((2^32-1)/d) + 1) is exact whenever n * d < 2^32
+// (Granlund-Montgomery, round-up variant).  d == 1 is handled by a mask.
+struct FastDiv {
+  uint32_t m;
+  uint32_t mask;
+  __host__ __device__ static FastDiv make(uint32_t d) {
+    FastDiv f;
+    if (d <= 1u) {
+      f.m = 0u;
+      f.mask = 0xFFFFFFFFu;
+    } else {
+      f.m = 0xFFFFFFFFu / d + 1u;
+      f.mask = 0u;
+    }
+    return f;
+  }
+  __device__ __forceinline__ uint32_t div(uint32_t n) const { return __umulhi(n, m) + (n & mask); }
+};
+
+// A box of cells in tile-local coordinates, x fastest.
+struct Box {
+  int e[3];
+  int count;
+  FastDiv d0;   // / e[0]
+  FastDiv d01;  // / (e[0]*e[1])
+  __device__ __forceinline__ void coords(int l, int& i, int& j, int& k) const {
+    uint32_t kk = d01.div((uint32_t)l);
+    uint32_t rem = (uint32_t)l - kk * (uint32_t)(e[0] * e[1]);
+    uint32_t jj = d0.div(rem);
+    i = (int)(rem - jj * (uint32_t)e[0]);
+    j = (int)jj;
+    k = (int)kk;
+  }
+};
+
+// Map a possibly out-of-range cell index onto the mesh along one axis.
+__device__ __forceinline__ int map_index(int p, int n, int bc) {
+  if (bc == kOutflow) return p < 0 ? 0 : (p >= n ? n - 1 : p);
+  if (n >= 8) {
+    p += (p < 0) ? n : 0;
+    p -= (p >= n) ? n : 0;
+    return p;
+  }
+  int r = p % n;
+  return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------
+// floating-point helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Fp;
+
+template <>
+struct Fp<float> {
+  // hardware reciprocal and square root (1 ulp); the FP32 path is held to a
+  // relative error budget, not to correct rounding
+  static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+  static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
+  // true when a and b carry the same sign bit
+  static __device__ __forceinline__ bool same_sign(float a, float b) {
+    return (__float_as_int(a) ^ __float_as_int(b)) >= 0;
+  }
+};
+
+template <>
+struct Fp<double> {
+  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+  static __device__ __forceinline__ bool same_sign(double a, double b) {
+    return (__double2hiint(a) ^ __double2hiint(b)) >= 0;
+  }
+};
+
+// Constants of the gas, each computed in FP64 on the host and rounded once.
+template <typename T>
+struct Gas {
+  T gamma;
+  T gm1;      // gamma - 1
+  T inv_gm1;  // 1 / (gamma - 1)
+};
+
+// Limited slope of the Interpolate equation: 0 when the one-sided
+// differences differ in sign (or one is zero), otherwise the one of smaller
+// magnitude.  copysign(min(|a|,|b|), a) equals that choice bit for bit, ties
+// included, and needs no product (so no underflow to a false zero).
+template <typename T>
+__device__ __forceinline__ T minmod(T a, T b) {
+  T m = fmin(fabs(a), fabs(b));
+  return Fp<T>::same_sign(a, b) ? copysign(m, a) : T(0);
+}
+
+// V(U): rho, v_a = m_a / rho, p = (gamma-1)(E - rho v^2/2).
+template <typename T, int D>
+__device__ __forceinline__ void prim_of_cons(const T* u, T* v, const Gas<T>& g) {
+  const T rho = u[0];
+  const T ir = Fp<T>::rcp(rho);
+  T ke = T(0);
+  v[0] = rho;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const T va = u[1 + a] * ir;
+    v[1 + a] = va;
+    ke += va * u[1 + a];
+  }
+  v[D + 1] = g.gm1 * (u[D + 1] - T(0.5) * ke);
+}
+
+// Reconstructed face states at the face between cells y1 and y2 of the
+// four-cell stencil y0 y1 | y2 y3 along the face normal.
+template <typename T>
+__device__ __forceinline__ void face_states(T y0, T y1, T y2, T y3, T& left, T& right) {
+  const T d12 = y2 - y1;
+  left = y1 + T(0.5) * minmod(y1 - y0, d12);
+  right = y2 - T(0.5) * minmod(d12, y3 - y2);
+}
+
+// HLLC flux across a face normal to axis AX.  vl / vr: primitive states on
+// the left / right of the face; f: conserved-ordered flux.
+//   c_K = sqrt(gamma p_K / rho_K); S_L = min(u_L - c_L, u_R - c_R),
+//   S_R = max(u_L + c_L, u_R + c_R) (Davis);
+//   S* = (p_R - p_L + rho_L u_L (S_L - u_L) - rho_R u_R (S_R - u_R))
+//        / (rho_L (S_L - u_L) - rho_R (S_R - u_R));
+//   F = F_L if 0 <= S_L; F_R if S_R <= 0; else F_K + S_K (U*_K - U_K) with
+//   K = L if 0 <= S*, else R, and
+//   U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S*, v_t, E_K/rho_K
+//          + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K)))).
+// The side is selected first so that one physical flux and one star state
+// are evaluated; E*_K is formed with the single reciprocal 1/(S_K - S*).
+template <typename T, int D, int AX>
+__device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T>& g) {
+  const T rl = vl[0], rr = vr[0];
+  const T ul = vl[1 + AX], ur = vr[1 + AX];
+  const T pl = vl[D + 1], pr = vr[D + 1];
+  const T cl = Fp<T>::sqrt(g.gamma * pl * Fp<T>::rcp(rl));
+  const T cr = Fp<T>::sqrt(g.gamma * pr * Fp<T>::rcp(rr));
+  const T sl = fmin(ul - cl, ur - cr);
+  const T sr = fmax(ul + cl, ur + cr);
+  const T al = rl * (sl - ul);
+  const T ar = rr * (sr - ur);
+  const T sstar = Fp<T>::div(pr - pl + al * ul - ar * ur, al - ar);
+
+  const bool left_sup = (T(0) <= sl);
+  const bool right_sup = (sr <= T(0));
+  const bool use_l = left_sup || (!right_sup && (T(0) <= sstar));
+
+  T vk[D + 2];
+#pragma unroll
+  for (int q = 0; q < D + 2; ++q) vk[q] = use_l ? vl[q] : vr[q];
+  const T sk = use_l ? sl : sr;
+  const T ak = use_l ? al : ar;
+  const T rk = vk[0], uk = vk[1 + AX], pk = vk[D + 1];
+
+  T v2 = T(0);
+#pragma unroll
+  for (int b = 0; b < D; ++b) v2 += vk[1 + b] * vk[1 + b];
+  const T ek = pk * g.inv_gm1 + T(0.5) * rk * v2;
+
+  // weight of the star correction: zero on supersonic faces
+  const bool sup = left_sup || right_sup;
+  const T w = sup ? T(0) : sk;
+  const T inv = sup ? T(0) : Fp<T>::rcp(sk - sstar);
+  const T rstar = ak * inv;
+  const T estar = inv * ((sk - uk) * ek + (sstar - uk) * (ak * sstar + pk));
+
+  // F_K + w (U*_K - U_K)
+  f[0] = uk * rk + w * (rstar - rk);
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const T mk = rk * vk[1 + b];
+    const T fk = uk * mk + (b == AX ? pk : T(0));
+    const T mstar = rstar * (b == AX ? sstar : vk[1 + b]);
+    f[1 + b] = fk + w * (mstar - mk);
+  }
+  f[D + 1] = uk * (ek + pk) + w * (estar - ek);
+}
+
+// CFL quantity sum_a (|v_a| + c)/dx_a of one cell, in FP64; returns a
+// negative value for a non-physical or non-finite state.
+template <typename T, int D>
+__device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double gamma) {
+  double ud[D + 2];
+#pragma unroll
+  for (int q = 0; q < D + 2; ++q) ud[q] = (double)u[q];
+  const double rho = ud[0];
+  const double ir = 1.0 / rho;
+  double ke = 0.0;
+  double vel[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    vel[a] = ud[1 + a] * ir;
+    ke += vel[a] * ud[1 + a];
+  }
+  const double p = (gamma - 1.0) * (ud[D + 1] - 0.5 * ke);
+  const double cs = ::sqrt(gamma * p * ir);
+  double q = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) q += (fabs(vel[a]) + cs) * inv_dx[a];
+  const bool ok = (rho > 0.0) && (p > 0.0) && isfinite(q) && isfinite(ud[D + 1]);
+  return ok ? q : -1.0;
+}
+
+}  // namespace paraiso

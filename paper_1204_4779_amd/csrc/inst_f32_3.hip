@@ -1,0 +1,24 @@
+// Kernel instantiations for float, 3D.
+#include "euler_kernels.h"
+#include "kernel_table.h"
+
+namespace paraiso {
+
+#define PARAISO_SET(K) {(const void*)K<float, 3, 0>, (const void*)K<float, 3, 1>, \
+                        (const void*)K<float, 3, 2>, (const void*)K<float, 3, 4>}
+
+const KernelTable* table_f32_3() {
+  static const KernelTable t = {
+      PARAISO_SET(k_stage_direct),
+      PARAISO_SET(k_stage_lds),
+      PARAISO_SET(k_fused_lds),
+      PARAISO_SET(k_fused_direct),
+      (const void*)k_cfl<float, 3>,
+      (const void*)k_totals_partial<float, 3>,
+      (const void*)k_totals_final<3>,
+      (int)sizeof(float),
+  };
+  return &t;
+}
+
+}  // namespace paraiso

@@ -1,0 +1,24 @@
+// Kernel instantiations for double, 1D.
+#include "euler_kernels.h"
+#include "kernel_table.h"
+
+namespace paraiso {
+
+#define PARAISO_SET(K) {(const void*)K<double, 1, 0>, (const void*)K<double, 1, 1>, \
+                        (const void*)K<double, 1, 2>, (const void*)K<double, 1, 4>}
+
+const KernelTable* table_f64_1() {
+  static const KernelTable t = {
+      PARAISO_SET(k_stage_direct),
+      PARAISO_SET(k_stage_lds),
+      PARAISO_SET(k_fused_lds),
+      PARAISO_SET(k_fused_direct),
+      (const void*)k_cfl<double, 1>,
+      (const void*)k_totals_partial<double, 1>,
+      (const void*)k_totals_final<1>,
+      (int)sizeof(double),
+  };
+  return &t;
+}
+
+}  // namespace paraiso

@@ -1,0 +1,24 @@
+// Kernel instantiations for double, 3D.
+#include "euler_kernels.h"
+#include "kernel_table.h"
+
+namespace paraiso {
+
+#define PARAISO_SET(K) {(const void*)K<double, 3, 0>, (const void*)K<double, 3, 1>, \
+                        (const void*)K<double, 3, 2>, (const void*)K<double, 3, 4>}
+
+const KernelTable* table_f64_3() {
+  static const KernelTable t = {
+      PARAISO_SET(k_stage_direct),
+      PARAISO_SET(k_stage_lds),
+      PARAISO_SET(k_fused_lds),
+      PARAISO_SET(k_fused_direct),
+      (const void*)k_cfl<double, 3>,
+      (const void*)k_totals_partial<double, 3>,
+      (const void*)k_totals_final<3>,
+      (int)sizeof(double),
+  };
+  return &t;
+}
+
+}  // namespace paraiso

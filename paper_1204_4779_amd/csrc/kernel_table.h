@@ -1,0 +1,27 @@
+// Table of kernel entry points for one (element type, dimension) pair.
+#pragma once
+
+namespace paraiso {
+
+// index of a waves-per-EU hint in the tables: 0 (compiler), 1, 2, 4
+inline int waves_slot(int w) { return w == 1 ? 1 : (w == 2 ? 2 : (w == 4 ? 3 : 0)); }
+
+struct KernelTable {
+  const void* stage_direct[4];
+  const void* stage_lds[4];
+  const void* fused_lds[4];
+  const void* fused_direct[4];
+  const void* cfl;
+  const void* totals_partial;
+  const void* totals_final;
+  int elem_bytes;
+};
+
+const KernelTable* table_f32_1();
+const KernelTable* table_f32_2();
+const KernelTable* table_f32_3();
+const KernelTable* table_f64_1();
+const KernelTable* table_f64_2();
+const KernelTable* table_f64_3();
+
+}  // namespace paraiso

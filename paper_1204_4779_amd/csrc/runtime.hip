@@ -1,0 +1,688 @@
+// Host runtime and C ABI of the Euler-step library (see include/paraiso.h).
+//
+// The runtime validates descriptors, lays out the caller's workspace, picks
+// and launches kernels for the selected variant, keeps the time-stepping
+// state on the device, and replays captured HIP graphs of six steps (the
+// period of the buffer ping-pong times the 3-slot control ring).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "euler_kernels.h"
+#include "kernel_table.h"
+#include "paraiso.h"
+
+using namespace paraiso;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(PARAISO_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+const KernelTable* table_for(int dtype, int ndim) {
+  if (dtype == PARAISO_F32) {
+    if (ndim == 1) return table_f32_1();
+    if (ndim == 2) return table_f32_2();
+    return table_f32_3();
+  }
+  if (ndim == 1) return table_f64_1();
+  if (ndim == 2) return table_f64_2();
+  return table_f64_3();
+}
+
+int64_t cells_of(const paraiso_mesh& m) { return m.n[0] * m.n[1] * m.n[2]; }
+
+int validate_mesh(const paraiso_mesh& m, int idx) {
+  const std::string w = "mesh " + std::to_string(idx) + ": ";
+  if (m.ndim < 1 || m.ndim > 3) return fail(PARAISO_ERR_INVALID_ARG, w + "ndim must be 1, 2 or 3");
+  if (m.dtype != PARAISO_F32 && m.dtype != PARAISO_F64)
+    return fail(PARAISO_ERR_INVALID_ARG, w + "dtype must be PARAISO_F32 or PARAISO_F64");
+  if (!(m.gamma > 1.0) || !std::isfinite(m.gamma))
+    return fail(PARAISO_ERR_INVALID_ARG, w + "gamma must be finite and > 1");
+  for (int a = 0; a < 3; ++a) {
+    if (m.n[a] < 1) return fail(PARAISO_ERR_INVALID_ARG, w + "n[a] must be >= 1");
+    if (a >= m.ndim) {
+      if (m.n[a] != 1) return fail(PARAISO_ERR_INVALID_ARG, w + "n[a] must be 1 for a >= ndim");
+      continue;
+    }
+    if (!(m.dx[a] > 0.0) || !std::isfinite(m.dx[a]))
+      return fail(PARAISO_ERR_INVALID_ARG, w + "dx[a] must be finite and > 0");
+    if (m.bc[a] != PARAISO_PERIODIC && m.bc[a] != PARAISO_OUTFLOW)
+      return fail(PARAISO_ERR_INVALID_ARG, w + "bc[a] must be PARAISO_PERIODIC or PARAISO_OUTFLOW");
+  }
+  if (m.n[0] > (1 << 30) || m.n[1] > (1 << 30) || m.n[2] > (1 << 30) || cells_of(m) >= (int64_t(1) << 31))
+    return fail(PARAISO_ERR_UNSUPPORTED, w + "more than 2^31 - 1 cells");
+  const size_t esz = m.dtype == PARAISO_F32 ? 4 : 8;
+  const size_t bytes = (size_t)cells_of(m) * esz;
+  const int nf = m.ndim + 2;
+  std::vector<std::pair<uintptr_t, uintptr_t>> ranges;
+  for (int b = 0; b < 2; ++b)
+    for (int q = 0; q < nf; ++q) {
+      const uintptr_t p = (uintptr_t)m.state[b][q];
+      if (!p) return fail(PARAISO_ERR_INVALID_ARG, w + "null state pointer");
+      if (p % 16) return fail(PARAISO_ERR_INVALID_ARG, w + "state arrays must be 16-byte aligned");
+      ranges.push_back({p, p + bytes});
+    }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t k = 1; k < ranges.size(); ++k)
+    if (ranges[k].first < ranges[k - 1].second)
+      return fail(PARAISO_ERR_INVALID_ARG, w + "state arrays overlap");
+  return PARAISO_OK;
+}
+
+int validate_meshes(const paraiso_mesh* ms, int count) {
+  if (!ms) return fail(PARAISO_ERR_INVALID_ARG, "null mesh array");
+  if (count < 1) return fail(PARAISO_ERR_INVALID_ARG, "count must be >= 1");
+  for (int i = 0; i < count; ++i) {
+    int rc = validate_mesh(ms[i], i);
+    if (rc) return rc;
+    if (ms[i].ndim != ms[0].ndim || ms[i].dtype != ms[0].dtype)
+      return fail(PARAISO_ERR_INVALID_ARG, "all meshes of a batch must share ndim and dtype");
+  }
+  return PARAISO_OK;
+}
+
+struct Layout {
+  size_t meshes = 0, ctl = 0, params = 0, dt = 0, queue = 0, out = 0, partials = 0, u1 = 0, total = 0;
+  int total_chunks = 0;
+};
+
+Layout layout_of(const paraiso_mesh* ms, int count) {
+  Layout L;
+  size_t off = 0;
+  L.meshes = off;
+  off += align256(sizeof(MeshDev) * count);
+  L.ctl = off;
+  off += align256(sizeof(Ctl) * count);
+  L.params = off;
+  off += align256(sizeof(Params));
+  L.dt = off;
+  off += align256(sizeof(double) * count);
+  L.queue = off;
+  off += align256(sizeof(unsigned) * 48);
+  L.out = off;
+  off += align256(sizeof(double) * kMaxFields * count);
+  int chunks = 0;
+  for (int m = 0; m < count; ++m) chunks += (int)((cells_of(ms[m]) + kChunk - 1) / kChunk);
+  L.total_chunks = chunks;
+  L.partials = off;
+  off += align256(sizeof(double) * kMaxFields * (size_t)chunks);
+  L.u1 = off;
+  const size_t esz = ms[0].dtype == PARAISO_F32 ? 4 : 8;
+  for (int m = 0; m < count; ++m) off += (size_t)(ms[m].ndim + 2) * align256((size_t)cells_of(ms[m]) * esz);
+  L.total = off;
+  return L;
+}
+
+struct Launch {
+  const void* fn = nullptr;
+  dim3 grid, block;
+  size_t shmem = 0;
+  bool with_geom = false;
+};
+
+}  // namespace
+
+struct paraiso_ctx {
+  int count = 0, ndim = 0, dtype = 0, esize = 4;
+  std::vector<paraiso_mesh> meshes;
+  std::vector<MeshDev> hm;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L;
+  MeshDev* d_meshes = nullptr;
+  Ctl* d_ctl = nullptr;
+  Params* d_params = nullptr;
+  double* d_dt = nullptr;
+  unsigned* d_queue = nullptr;
+  double* d_out = nullptr;
+  double* d_partials = nullptr;
+  const KernelTable* tab = nullptr;
+  paraiso_variant var{};
+  bool fused = false, lds = false, persistent = false;
+  int nitems = 0;
+  int xcd_begin[9] = {};
+  LdsGeom geom{};
+  Launch step;  // fused kernel, or the stage kernel launched twice
+  int cur = 0, ring = 0;
+  hipGraphExec_t graph[6] = {};
+  int device = 0, num_cus = 0, max_lds = 0;
+};
+
+namespace {
+
+Box make_box(int e0, int e1, int e2) {
+  Box b;
+  b.e[0] = e0;
+  b.e[1] = e1;
+  b.e[2] = e2;
+  b.count = e0 * e1 * e2;
+  b.d0 = FastDiv::make((uint32_t)e0);
+  b.d01 = FastDiv::make((uint32_t)(e0 * e1));
+  return b;
+}
+
+void drop_graphs(paraiso_ctx* c) {
+  for (auto& g : c->graph) {
+    if (g) hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
+Args base_args(const paraiso_ctx* c) {
+  Args a{};
+  a.meshes = c->d_meshes;
+  a.ctl = c->d_ctl;
+  a.prm = c->d_params;
+  a.dt = nullptr;
+  a.queue = c->d_queue;
+  a.partials = c->d_partials;
+  a.nmeshes = c->count;
+  a.nitems = c->nitems;
+  for (int k = 0; k < 3; ++k) a.tile[k] = c->var.tile[k];
+  a.persistent = c->persistent ? 1 : 0;
+  for (int k = 0; k < 9; ++k) a.xcd_begin[k] = c->xcd_begin[k];
+  return a;
+}
+
+int launch(const Launch& l, Args a, const LdsGeom& g, hipStream_t s) {
+  void* args2[] = {(void*)&a, (void*)&g};
+  HIP_TRY(hipLaunchKernel(l.fn, l.grid, l.block, args2, l.shmem, s));
+  return PARAISO_OK;
+}
+
+// Enqueue one step in phase (cur, ring); explicit: dt from d_dt.
+int enqueue_step(const paraiso_ctx* c, int cur, int ring, bool explicit_dt, hipStream_t s) {
+  Args a = base_args(c);
+  a.dt = explicit_dt ? c->d_dt : nullptr;
+  a.src = cur;
+  a.ring = ring;
+  if (c->fused) {
+    a.stage = 0;
+    a.cfl = explicit_dt ? 0 : 1;
+    return launch(c->step, a, c->geom, s);
+  }
+  a.stage = 1;
+  a.cfl = 0;
+  int rc = launch(c->step, a, c->geom, s);
+  if (rc) return rc;
+  a.stage = 2;
+  a.cfl = explicit_dt ? 0 : 1;
+  return launch(c->step, a, c->geom, s);
+}
+
+int capture_graph(paraiso_ctx* c, int phase) {
+  const int cur0 = phase / 3, ring0 = phase % 3;
+  HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeRelaxed));
+  int rc = PARAISO_OK;
+  for (int s = 0; s < 6 && !rc; ++s) rc = enqueue_step(c, (cur0 + s) & 1, (ring0 + s) % 3, false, c->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->cap, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(PARAISO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->graph[phase], g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    c->graph[phase] = nullptr;
+    return fail(PARAISO_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return PARAISO_OK;
+}
+
+// Device-dt steps: whole six-step periods from the graph, the rest eagerly.
+int run_steps(paraiso_ctx* c, int64_t n) {
+  while (n >= 6) {
+    const int phase = c->cur * 3 + c->ring;
+    if (!c->graph[phase]) {
+      int rc = capture_graph(c, phase);
+      if (rc) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(c->graph[phase], c->stream));
+    n -= 6;
+  }
+  while (n > 0) {
+    int rc = enqueue_step(c, c->cur, c->ring, false, c->stream);
+    if (rc) return rc;
+    c->cur ^= 1;
+    c->ring = (c->ring + 1) % 3;
+    --n;
+  }
+  return PARAISO_OK;
+}
+
+int ctl_init(paraiso_ctx* c, const double* d_t0) {
+  const int blocks = (std::max(c->count, 48) + 255) / 256;
+  hipLaunchKernelGGL(k_ctl_init, dim3(blocks), dim3(256), 0, c->stream, c->d_ctl, d_t0, c->count, c->ring,
+                     c->d_queue);
+  HIP_TRY(hipGetLastError());
+  return PARAISO_OK;
+}
+
+int launch_cfl(paraiso_ctx* c) {
+  Args a = base_args(c);
+  a.src = c->cur;
+  a.ring = c->ring;
+  void* args[] = {(void*)&a};
+  HIP_TRY(hipLaunchKernel(c->tab->cfl, dim3(c->L.total_chunks), dim3(256), args, 0, c->stream));
+  return PARAISO_OK;
+}
+
+int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string& why) {
+  const int d = c->ndim;
+  for (int a = 0; a < 3; ++a) {
+    if (a < d && (v.tile[a] < 1 || v.tile[a] > 4096)) {
+      why = "tile[a] must be in [1, 4096] on active axes";
+      return PARAISO_ERR_UNSUPPORTED;
+    }
+    if (a >= d && v.tile[a] != 1) {
+      why = "tile[a] must be 1 on unused axes";
+      return PARAISO_ERR_UNSUPPORTED;
+    }
+  }
+  if (v.lds != 0 && v.lds != 1) return why = "lds must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
+  if (v.fuse != 0 && v.fuse != 1) return why = "fuse must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
+  if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
+  if (!(v.waves_per_eu == 0 || v.waves_per_eu == 1 || v.waves_per_eu == 2 || v.waves_per_eu == 4))
+    return why = "waves_per_eu must be 0, 1, 2 or 4", PARAISO_ERR_UNSUPPORTED;
+  if (v.threads != 0 && (v.threads < 64 || v.threads > 512 || v.threads % 64))
+    return why = "threads must be 0 or a multiple of 64 in [64, 512]", PARAISO_ERR_UNSUPPORTED;
+  const int64_t tc = (int64_t)v.tile[0] * v.tile[1] * v.tile[2];
+  if (tc > 65536) return why = "tile has more than 65536 cells", PARAISO_ERR_UNSUPPORTED;
+  return PARAISO_OK;
+}
+
+int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
+  std::string why;
+  paraiso_variant v = vin;
+  int rc = validate_variant(c, v, why);
+  if (rc) return fail(rc, "variant: " + why);
+  const int d = c->ndim, nf = d + 2;
+  const int threads = v.threads ? v.threads : 256;
+  // items
+  int64_t items = 0;
+  for (int m = 0; m < c->count; ++m) {
+    MeshDev& M = c->hm[m];
+    int64_t nt = 1;
+    for (int a = 0; a < 3; ++a) {
+      M.nt[a] = (int)((M.n[a] + v.tile[a] - 1) / v.tile[a]);
+      nt *= M.nt[a];
+    }
+    if (items + nt >= (int64_t(1) << 31)) return fail(PARAISO_ERR_UNSUPPORTED, "variant: too many tiles");
+    M.item0 = (int)items;
+    M.nitems = (int)nt;
+    items += nt;
+  }
+  const int nitems = (int)items;
+  // geometry
+  LdsGeom G{};
+  size_t shmem = 0;
+  const int H = v.fuse ? 4 : 2;
+  int e[3], t[3];
+  for (int a = 0; a < 3; ++a) {
+    t[a] = v.tile[a];
+    e[a] = a < d ? v.tile[a] + 2 * H : 1;
+  }
+  G.halo = H;
+  G.vin = make_box(e[0], e[1], e[2]);
+  G.tile = make_box(t[0], t[1], t[2]);
+  int c1[3];
+  for (int a = 0; a < 3; ++a) c1[a] = (v.fuse && a < d) ? t[a] + 4 : t[a];
+  G.c1 = make_box(c1[0], c1[1], c1[2]);
+  int fmax_count = 0;
+  for (int a = 0; a < 3; ++a) {
+    int f[3] = {c1[0], c1[1], c1[2]};
+    int f2[3] = {t[0], t[1], t[2]};
+    if (a < d) {
+      f[a] += 1;
+      f2[a] += 1;
+    }
+    G.fx[a] = make_box(f[0], f[1], f[2]);
+    G.fx2[a] = make_box(f2[0], f2[1], f2[2]);
+    if (a < d) fmax_count = std::max(fmax_count, std::max(G.fx[a].count, G.fx2[a].count));
+  }
+  G.vstride = G.vin.count;
+  G.fstride = fmax_count;
+  if (v.lds) {
+    shmem = (size_t)c->esize * nf * ((size_t)G.vstride + G.fstride);
+    const size_t static_lds = 16 * sizeof(double) + 64;
+    if (shmem + static_lds > (size_t)c->max_lds)
+      return fail(PARAISO_ERR_UNSUPPORTED, "variant: LDS tile needs " + std::to_string(shmem) + " bytes, limit " +
+                                               std::to_string(c->max_lds));
+    if (G.tile.count > kMaxR * threads || G.c1.count > kMaxR * threads)
+      return fail(PARAISO_ERR_UNSUPPORTED, "variant: more than " + std::to_string(kMaxR) +
+                                               " cells per thread; use more threads or a smaller tile");
+  }
+  // fused direct needs 4 cells of halo along each axis inside the mesh's
+  // periodic wrap; nothing else to check
+  const int ws = waves_slot(v.waves_per_eu);
+  Launch L;
+  if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
+  else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
+  L.block = dim3(threads);
+  L.shmem = shmem;
+  L.with_geom = true;
+  if (shmem > 65536) HIP_TRY(hipFuncSetAttribute(L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
+  // grid
+  int grid = nitems;
+  if (v.persistent) {
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, L.fn, threads, shmem));
+    if (per_cu < 1) return fail(PARAISO_ERR_UNSUPPORTED, "variant: kernel does not fit on a CU");
+    grid = std::min<int64_t>((int64_t)per_cu * c->num_cus, nitems);
+    grid = std::max(grid, 1);
+  }
+  L.grid = dim3(grid);
+  {
+    hipFuncAttributes fa{};
+    HIP_TRY(hipFuncGetAttributes(&fa, L.fn));
+    if (fa.maxThreadsPerBlock > 0 && threads > fa.maxThreadsPerBlock)
+      return fail(PARAISO_ERR_UNSUPPORTED, "variant: kernel allows at most " + std::to_string(fa.maxThreadsPerBlock) +
+                                               " threads per block");
+  }
+  // commit
+  const int per = nitems / 8, rem = nitems % 8;
+  for (int x = 0; x <= 8; ++x) c->xcd_begin[x] = x * per + std::min(x, rem);
+  HIP_TRY(hipMemcpyAsync(c->d_meshes, c->hm.data(), sizeof(MeshDev) * c->count, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drop_graphs(c);
+  v.threads = threads;
+  c->var = v;
+  c->fused = v.fuse != 0;
+  c->lds = v.lds != 0;
+  c->persistent = v.persistent != 0;
+  c->nitems = nitems;
+  c->geom = G;
+  c->step = L;
+  return PARAISO_OK;
+}
+
+void default_variant(int ndim, int dtype, paraiso_variant* v) {
+  std::memset(v, 0, sizeof(*v));
+  v->tile[0] = v->tile[1] = v->tile[2] = 1;
+  v->lds = 1;
+  v->threads = 256;
+  if (ndim == 1) {
+    v->tile[0] = 256;
+    v->fuse = 1;
+  } else if (ndim == 2) {
+    v->tile[0] = 32;
+    v->tile[1] = 16;
+    v->fuse = 1;
+  } else {
+    v->tile[0] = 16;
+    v->tile[1] = 8;
+    v->tile[2] = 4;
+    v->fuse = 0;
+  }
+  (void)dtype;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* paraiso_last_error(void) { return g_err.c_str(); }
+
+const char* paraiso_version(void) { return "paraiso-mi355x 0.1 (gfx950)"; }
+
+int32_t paraiso_workspace_bytes(const paraiso_mesh* meshes, int32_t count, size_t* bytes) {
+  if (!bytes) return fail(PARAISO_ERR_INVALID_ARG, "null output pointer");
+  int rc = validate_meshes(meshes, count);
+  if (rc) return rc;
+  *bytes = layout_of(meshes, count).total;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v) {
+  if (!v) return fail(PARAISO_ERR_INVALID_ARG, "null variant pointer");
+  int rc = validate_meshes(meshes, count);
+  if (rc) return rc;
+  default_variant(meshes[0].ndim, meshes[0].dtype, v);
+  if (count > 1) v->persistent = 1;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace, size_t workspace_bytes,
+                     void* hip_stream, paraiso_ctx** out) {
+  if (!out) return fail(PARAISO_ERR_INVALID_ARG, "null context pointer");
+  *out = nullptr;
+  int rc = validate_meshes(meshes, count);
+  if (rc) return rc;
+  if (!workspace) return fail(PARAISO_ERR_INVALID_ARG, "null workspace");
+  if ((uintptr_t)workspace % 256) return fail(PARAISO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  Layout L = layout_of(meshes, count);
+  if (workspace_bytes < L.total)
+    return fail(PARAISO_ERR_WORKSPACE, "workspace has " + std::to_string(workspace_bytes) + " bytes, needs " +
+                                           std::to_string(L.total));
+  paraiso_ctx* c = new (std::nothrow) paraiso_ctx();
+  if (!c) return fail(PARAISO_ERR_INVALID_ARG, "out of host memory");
+  c->count = count;
+  c->ndim = meshes[0].ndim;
+  c->dtype = meshes[0].dtype;
+  c->esize = c->dtype == PARAISO_F32 ? 4 : 8;
+  c->meshes.assign(meshes, meshes + count);
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (char*)workspace;
+  c->ws_bytes = workspace_bytes;
+  c->L = L;
+  c->d_meshes = (MeshDev*)(c->ws + L.meshes);
+  c->d_ctl = (Ctl*)(c->ws + L.ctl);
+  c->d_params = (Params*)(c->ws + L.params);
+  c->d_dt = (double*)(c->ws + L.dt);
+  c->d_queue = (unsigned*)(c->ws + L.queue);
+  c->d_out = (double*)(c->ws + L.out);
+  c->d_partials = (double*)(c->ws + L.partials);
+  c->tab = table_for(c->dtype, c->ndim);
+  auto bail = [&](int code) {
+    if (c->cap) hipStreamDestroy(c->cap);
+    delete c;
+    return code;
+  };
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("device query: ") + hipGetErrorString(e)));
+  // host mesh table
+  c->hm.resize(count);
+  size_t u1off = L.u1;
+  int chunk = 0;
+  for (int m = 0; m < count; ++m) {
+    const paraiso_mesh& pm = meshes[m];
+    MeshDev& M = c->hm[m];
+    std::memset(&M, 0, sizeof(M));
+    const int nf = pm.ndim + 2;
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < kMaxFields; ++q) M.s[b][q] = q < nf ? pm.state[b][q] : nullptr;
+    const size_t fbytes = align256((size_t)cells_of(pm) * c->esize);
+    for (int q = 0; q < kMaxFields; ++q) M.w[q] = q < nf ? (void*)(c->ws + u1off + q * fbytes) : nullptr;
+    u1off += nf * fbytes;
+    double vol = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      M.n[a] = (int)pm.n[a];
+      M.bc[a] = a < pm.ndim ? pm.bc[a] : PARAISO_PERIODIC;
+      M.dx[a] = a < pm.ndim ? pm.dx[a] : 1.0;
+      M.inv_dx[a] = 1.0 / M.dx[a];
+      if (a < pm.ndim) vol *= pm.dx[a];
+    }
+    M.gamma = pm.gamma;
+    M.vol = vol;
+    M.ncells = (int)cells_of(pm);
+    M.chunk0 = chunk;
+    M.nchunks = (M.ncells + kChunk - 1) / kChunk;
+    chunk += M.nchunks;
+  }
+  paraiso_variant v;
+  default_variant(c->ndim, c->dtype, &v);
+  if (count > 1) v.persistent = 1;
+  rc = apply_variant(c, v);
+  if (rc) return bail(rc);
+  rc = ctl_init(c, nullptr);
+  if (rc) return bail(rc);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
+  *out = c;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_set_variant(paraiso_ctx* c, const paraiso_variant* v) {
+  if (!c || !v) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  paraiso_variant old = c->var;
+  int rc = apply_variant(c, *v);
+  if (rc) {
+    std::string msg = g_err;
+    apply_variant(c, old);
+    g_err = msg;
+  }
+  return rc;
+}
+
+int32_t paraiso_get_variant(const paraiso_ctx* c, paraiso_variant* v) {
+  if (!c || !v) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  *v = c->var;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_current(const paraiso_ctx* c, int32_t* idx) {
+  if (!c || !idx) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  *idx = c->cur;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_cfl_dt(paraiso_ctx* c, double cfl, double* dt_out) {
+  if (!c || !dt_out) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (!(cfl > 0.0 && cfl <= 1.0)) return fail(PARAISO_ERR_INVALID_ARG, "cfl must be in (0, 1]");
+  int rc = ctl_init(c, nullptr);
+  if (!rc) rc = launch_cfl(c);
+  if (rc) return rc;
+  std::vector<Ctl> h(c->count);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int m = 0; m < c->count; ++m) {
+    if (h[m].flags) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": non-physical state");
+    uint64_t bits = h[m].qbits[c->ring];
+    double q;
+    std::memcpy(&q, &bits, sizeof(q));
+    if (!(q > 0.0)) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": no signal speed");
+    dt_out[m] = cfl / q;
+  }
+  return PARAISO_OK;
+}
+
+int32_t paraiso_step(paraiso_ctx* c, const double* dt) {
+  if (!c || !dt) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  for (int m = 0; m < c->count; ++m)
+    if (!(dt[m] >= 0.0) || !std::isfinite(dt[m])) return fail(PARAISO_ERR_INVALID_ARG, "dt must be finite and >= 0");
+  HIP_TRY(hipMemcpyAsync(c->d_dt, dt, sizeof(double) * c->count, hipMemcpyHostToDevice, c->stream));
+  int rc = enqueue_step(c, c->cur, c->ring, true, c->stream);
+  if (rc) return rc;
+  c->cur ^= 1;
+  c->ring = (c->ring + 1) % 3;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_steps, double* t_inout,
+                        int64_t* steps_out) {
+  if (!c || !t_inout || !steps_out) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (!(cfl > 0.0 && cfl <= 1.0)) return fail(PARAISO_ERR_INVALID_ARG, "cfl must be in (0, 1]");
+  if (max_steps < 0) return fail(PARAISO_ERR_INVALID_ARG, "max_steps must be >= 0");
+  if (std::isnan(t_end) || t_end == -INFINITY) return fail(PARAISO_ERR_INVALID_ARG, "t_end must be a number or +inf");
+  for (int m = 0; m < c->count; ++m)
+    if (!std::isfinite(t_inout[m])) return fail(PARAISO_ERR_INVALID_ARG, "t_inout must be finite");
+  Params p{t_end, cfl, (long long)max_steps};
+  HIP_TRY(hipMemcpyAsync(c->d_params, &p, sizeof(p), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_dt, t_inout, sizeof(double) * c->count, hipMemcpyHostToDevice, c->stream));
+  int rc = ctl_init(c, c->d_dt);
+  if (!rc) rc = launch_cfl(c);
+  if (rc) return rc;
+  std::vector<Ctl> h(c->count);
+  std::vector<double> t0(t_inout, t_inout + c->count);
+  int64_t launched = 0;
+  int64_t chunk = std::isinf(t_end) ? max_steps : std::min<int64_t>(max_steps, 32);
+  for (;;) {
+    rc = run_steps(c, chunk);
+    if (rc) return rc;
+    launched += chunk;
+    HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool done = true;
+    int64_t want = 0;
+    for (int m = 0; m < c->count; ++m) {
+      if (h[m].flags) {
+        for (int k = 0; k < c->count; ++k) {
+          t_inout[k] = h[k].t[c->ring];
+          steps_out[k] = h[k].steps[c->ring];
+        }
+        return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": non-physical state");
+      }
+      const double t = h[m].t[c->ring];
+      const int64_t st = h[m].steps[c->ring];
+      if (t < t_end && st < max_steps) {
+        done = false;
+        int64_t est = max_steps - st;
+        if (st > 0 && t > t0[m]) {
+          const double avg = (t - t0[m]) / (double)st;
+          const double need = std::ceil((t_end - t) / avg * 1.05) + 2.0;
+          if (need < (double)est) est = (int64_t)need;
+        }
+        want = std::max(want, est);
+      }
+    }
+    if (done) break;
+    chunk = std::max<int64_t>(1, std::min<int64_t>(want, max_steps));
+  }
+  for (int m = 0; m < c->count; ++m) {
+    t_inout[m] = h[m].t[c->ring];
+    steps_out[m] = h[m].steps[c->ring];
+  }
+  return PARAISO_OK;
+}
+
+int32_t paraiso_totals(paraiso_ctx* c, double* out) {
+  if (!c || !out) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  Args a = base_args(c);
+  a.src = c->cur;
+  void* args[] = {(void*)&a};
+  HIP_TRY(hipLaunchKernel(c->tab->totals_partial, dim3(c->L.total_chunks), dim3(256), args, 0, c->stream));
+  void* args2[] = {(void*)&a, (void*)&c->d_out};
+  HIP_TRY(hipLaunchKernel(c->tab->totals_final, dim3(c->count), dim3(256), args2, 0, c->stream));
+  const int nf = c->ndim + 2;
+  std::vector<double> h((size_t)c->count * nf);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->d_out, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  std::memcpy(out, h.data(), sizeof(double) * h.size());
+  return PARAISO_OK;
+}
+
+int32_t paraiso_destroy(paraiso_ctx* c) {
+  if (!c) return PARAISO_OK;
+  drop_graphs(c);
+  if (c->cap) hipStreamDestroy(c->cap);
+  delete c;
+  return PARAISO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+"""The C ABI without a GPU: the library loads, exports what include/paraiso.h declares,
+and its host-side validation returns the documented status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1204_4779_amd import binding as pb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "paraiso.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pb.LIB_PATH):
+        from paper_1204_4779_amd import build
+        build.build(verbose=False)
+    return pb.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(paraiso_[a-z_]+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_binding_names():
+    assert set(declared_functions()) == set(pb.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _mesh(ndim=2, n=(8, 8, 1), dtype=pb.F32, gamma=1.4, bc=(0, 0, 0), base=0x10000, dx=None):
+    m = pb.paraiso_mesh()
+    m.ndim, m.dtype, m.gamma = ndim, dtype, gamma
+    for a in range(3):
+        m.n[a] = n[a]
+        m.dx[a] = (dx[a] if dx else 1.0 / max(n[a], 1))
+        m.bc[a] = bc[a]
+    cells = max(n[0] * n[1] * n[2], 1)
+    esz = 4 if dtype == pb.F32 else 8
+    p = base
+    for b in range(2):
+        for q in range(min(max(ndim, 1) + 2, 5)):
+            m.state[b][q] = p
+            p += ((cells * esz + 255) // 256) * 256
+    return m
+
+
+def test_workspace_bytes_valid(lib):
+    assert pb.paraiso_workspace_bytes([_mesh()]) > 8 * 8 * 4 * 4
+    assert pb.paraiso_workspace_bytes([_mesh(3, (4, 5, 6), pb.F64), _mesh(3, (7, 2, 3), pb.F64)]) > 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(ndim=0), dict(ndim=4), dict(gamma=1.0), dict(gamma=float("nan")), dict(n=(0, 8, 1)),
+    dict(ndim=2, n=(8, 8, 2)), dict(bc=(2, 0, 0)), dict(dtype=7), dict(dx=(0.0, 1.0, 1.0)),
+    dict(dx=(float("inf"), 1.0, 1.0)),
+])
+def test_workspace_bytes_rejects_invalid_mesh(lib, bad):
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_workspace_bytes([_mesh(**bad)])
+    assert ei.value.code == pb.ERR_INVALID_ARG
+    assert lib.paraiso_last_error().decode() != ""
+
+
+def test_rejects_null_and_overlapping_buffers(lib):
+    m = _mesh()
+    m.state[1][0] = None
+    with pytest.raises(pb.ParaisoError):
+        pb.paraiso_workspace_bytes([m])
+    m = _mesh()
+    m.state[1][2] = m.state[0][1]
+    with pytest.raises(pb.ParaisoError):
+        pb.paraiso_workspace_bytes([m])
+    m = _mesh()
+    m.state[0][0] = m.state[0][0] + 4  # misaligned
+    with pytest.raises(pb.ParaisoError):
+        pb.paraiso_workspace_bytes([m])
+
+
+def test_rejects_mixed_batch(lib):
+    with pytest.raises(pb.ParaisoError):
+        pb.paraiso_workspace_bytes([_mesh(), _mesh(ndim=3, n=(4, 4, 4), base=0x900000)])
+
+
+def test_too_many_cells_unsupported(lib):
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_workspace_bytes([_mesh(3, (2048, 2048, 1024))])
+    assert ei.value.code == pb.ERR_UNSUPPORTED
+
+
+def test_init_argument_errors_before_device_work(lib):
+    arr = (pb.paraiso_mesh * 1)(_mesh())
+    ctx = ctypes.c_void_p()
+    assert lib.paraiso_init(arr, 1, None, 1 << 20, None, ctypes.byref(ctx)) == pb.ERR_INVALID_ARG
+    assert lib.paraiso_init(arr, 1, ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(ctx)) == pb.ERR_INVALID_ARG
+    assert lib.paraiso_init(arr, 1, ctypes.c_void_p(0x100000), 16, None, ctypes.byref(ctx)) == pb.ERR_WORKSPACE
+    assert lib.paraiso_init(arr, 0, ctypes.c_void_p(0x100000), 1 << 20, None, ctypes.byref(ctx)) == pb.ERR_INVALID_ARG
+    assert lib.paraiso_destroy(None) == pb.OK
+
+
+def test_default_variant(lib):
+    v = pb.paraiso_default_variant([_mesh()])
+    assert v.lds in (0, 1) and v.fuse in (0, 1) and v.tile[2] == 1
+    v3 = pb.paraiso_default_variant([_mesh(3, (4, 4, 4))])
+    assert all(t >= 1 for t in v3.tile)
+
+
+def test_version(lib):
+    assert "gfx950" in pb.paraiso_version()

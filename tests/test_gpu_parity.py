@@ -1,0 +1,213 @@
+"""HIP path vs the FP64 oracle, through the C ABI (paraiso_*).
+
+One step from identical input with an explicit dt (the oracle's CFL step):
+FP64 within 1e-12 and FP32 within 1e-5, normwise relative per field, for
+every kernel variant, dimension and boundary condition, on meshes that span
+several tiles and end in a ragged tile.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_4779_amd import binding as pb
+from paper_1204_4779_amd import inputs
+
+from gpu_util import (TOL, VARIANTS, as_input, default_tile, gpu_solver, gpu_state, oracle_mesh, rel_err,
+                      spec_of)
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = {1: (203,), 2: (37, 21), 3: (19, 11, 10)}
+
+
+def _variant(name, ndim, tile=None):
+    v = dict(VARIANTS[name])
+    v["tile"] = tile or default_tile(ndim)
+    return v
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("vname", list(VARIANTS))
+def test_one_step_matches_oracle(dtype, ndim, bc, vname):
+    print(f"case dtype={dtype} ndim={ndim} bc={bc} variant={vname}", flush=True)
+    pr = inputs.random_state(ndim, SHAPES[ndim], seed=100 + 10 * ndim + bc, rough=(ndim != 3),
+                             bc=(bc,) * 3)
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.5)
+    ref = oracle.step(m, U0, dt)
+    s = gpu_solver(spec_of(pr), dtype, _variant(vname, ndim), pr.U)
+    s.step(dt)
+    got = gpu_state(s)
+    err = rel_err(got, ref)
+    print(f"  rel err {err:.3e}", flush=True)
+    assert err <= TOL[dtype], err
+    # the step did something
+    assert rel_err(ref, U0) > 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_smooth_2d_many_tiles_and_persistent(dtype):
+    pr = inputs.random_state(2, (133, 70), seed=7, bc=(0, 1))
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.4)
+    ref = oracle.step(m, U0, dt)
+    for v in (dict(tile=(32, 16), lds=1, fuse=1, persistent=1),
+              dict(tile=(16, 16), lds=1, fuse=0, persistent=1, threads=128),
+              dict(tile=(64, 8), lds=1, fuse=1, waves_per_eu=2, threads=512)):
+        s = gpu_solver(spec_of(pr), dtype, v, pr.U)
+        s.step(dt)
+        assert rel_err(gpu_state(s), ref) <= TOL[dtype], v
+
+
+@pytest.mark.parametrize("ndim,n", [(1, (1,)), (1, (3,)), (2, (5, 2)), (3, (3, 2, 5))])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_tiny_meshes(ndim, n, bc):
+    pr = inputs.random_state(ndim, n, seed=3, bc=(bc,) * 3)
+    m = oracle_mesh(pr)
+    dt = 1e-3
+    ref = oracle.step(m, pr.U, dt)
+    for vname in VARIANTS:
+        s = gpu_solver(spec_of(pr), "f64", _variant(vname, ndim), pr.U)
+        s.step(dt)
+        assert rel_err(gpu_state(s), ref) <= 1e-12, vname
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_uniform_flow_bitwise(dtype, ndim):
+    pr = inputs.uniform_flow(ndim, SHAPES[ndim], bc=(1, 0, 1))
+    for vname in VARIANTS:
+        s = gpu_solver(spec_of(pr), dtype, _variant(vname, ndim), pr.U)
+        s.step(2e-3)
+        np.testing.assert_array_equal(gpu_state(s), as_input(pr.U, dtype))
+
+
+def test_zero_dt_is_identity():
+    pr = inputs.random_state(2, (40, 30), seed=4, rough=True)
+    for vname in VARIANTS:
+        s = gpu_solver(spec_of(pr), "f64", _variant(vname, 2), pr.U)
+        s.step(0.0)
+        np.testing.assert_array_equal(gpu_state(s), pr.U)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_cfl_dt_matches_oracle(dtype, ndim):
+    pr = inputs.random_state(ndim, SHAPES[ndim], seed=17, rough=True)
+    U0 = as_input(pr.U, dtype)
+    want = oracle.cfl_dt(oracle_mesh(pr), U0, 0.5)
+    s = gpu_solver(spec_of(pr), dtype, None, pr.U)
+    got = s.cfl_dt(0.5)[0]
+    assert abs(got - want) <= 1e-14 * want
+
+
+def test_cfl_flags_nonphysical():
+    pr = inputs.random_state(2, (30, 20), seed=5)
+    bad = pr.U.copy()
+    bad[0, 7, 3] = -0.5
+    s = gpu_solver(spec_of(pr), "f64", None, bad)
+    with pytest.raises(FloatingPointError):
+        s.cfl_dt(0.5)
+    bad = pr.U.copy()
+    bad[3, 1, 1] = np.nan
+    s = gpu_solver(spec_of(pr), "f32", None, bad)
+    with pytest.raises(FloatingPointError):
+        s.cfl_dt(0.5)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_totals_match_oracle(dtype, ndim):
+    pr = inputs.random_state(ndim, SHAPES[ndim], seed=23)
+    U0 = as_input(pr.U, dtype)
+    want = oracle.totals(oracle_mesh(pr), U0)
+    s = gpu_solver(spec_of(pr), dtype, None, pr.U)
+    got = np.array(s.totals()[0])
+    np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("vname", ["lds_fused", "lds", "direct"])
+def test_sod_advance_matches_oracle_and_exact(vname):
+    from oracle import exact_riemann as er
+    pr = inputs.sod_1d(1024)
+    ref, t_ref, steps_ref = oracle.advance(oracle_mesh(pr), pr.U, 0.5, 0.2)
+    s = gpu_solver(spec_of(pr), "f64", _variant(vname, 1, tile=(256, 1, 1)), pr.U)
+    t, steps = s.advance(0.2, 0.5)
+    got = gpu_state(s)
+    assert t[0] == 0.2 and steps[0] == steps_ref
+    assert rel_err(got, ref) < 1e-10
+    x = inputs.centres(1024)
+    rho_ex = np.array([e[0] for e in er.sample_cells(1.4, er.Side(1, 0, 1), er.Side(0.125, 0, 0.1), 0.5, 0.2, x)])
+    assert np.mean(np.abs(got[0] - rho_ex)) < 5e-3
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_advance_graph_equals_eager_and_is_deterministic(dtype):
+    pr = inputs.random_state(2, (96, 64), seed=31)
+    spec = spec_of(pr)
+    a = gpu_solver(spec, dtype, None, pr.U)
+    ta, na = a.advance(float("inf"), 0.5, max_steps=12)   # two six-step graph replays
+    b = gpu_solver(spec, dtype, None, pr.U)
+    t = [0.0]
+    for k in (5, 5, 2):                                    # eager launches only
+        t, _ = b.advance(float("inf"), 0.5, max_steps=k, t0=t)
+    c = gpu_solver(spec, dtype, None, pr.U)
+    tc, _ = c.advance(float("inf"), 0.5, max_steps=12)
+    assert na == [12]
+    np.testing.assert_array_equal(gpu_state(a), gpu_state(c))
+    assert ta == tc
+    np.testing.assert_array_equal(gpu_state(a), gpu_state(b))
+    assert ta == t
+
+
+def test_advance_matches_oracle_steps_2d():
+    pr = inputs.random_state(2, (48, 40), seed=41, bc=(1, 0))
+    ref, t_ref, n_ref = oracle.advance(oracle_mesh(pr), pr.U, 0.5, 1e9, max_steps=10)
+    for v in (dict(tile=(16, 8), lds=1, fuse=1), dict(tile=(16, 8), lds=1, fuse=0)):
+        s = gpu_solver(spec_of(pr), "f64", v, pr.U)
+        t, n = s.advance(1e9, 0.5, max_steps=10)
+        assert n == [10]
+        assert abs(t[0] - t_ref) <= 1e-13 * t_ref
+        assert rel_err(gpu_state(s), ref) < 1e-11
+
+
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_batch_members_equal_solo_runs(persistent):
+    sizes = [(20, 17), (64, 64), (9, 31), (50, 8)]
+    probs = [inputs.random_state(2, n, seed=60 + k) for k, n in enumerate(sizes)]
+    specs = [spec_of(p) for p in probs]
+    dts = [oracle.cfl_dt(oracle_mesh(p), as_input(p.U, "f32"), 0.5) for p in probs]
+    v = dict(tile=(16, 8), lds=1, fuse=1, persistent=persistent)
+    b = gpu_solver(specs, "f32", v, [p.U for p in probs])
+    b.step(dts)
+    for k, p in enumerate(probs):
+        solo = gpu_solver(specs[k], "f32", v, p.U)
+        solo.step(dts[k])
+        np.testing.assert_array_equal(gpu_state(b, k), gpu_state(solo))
+        ref = oracle.step(oracle_mesh(p), as_input(p.U, "f32"), dts[k])
+        assert rel_err(gpu_state(b, k), ref) <= TOL["f32"]
+
+
+def test_batch_advance_per_mesh_dt():
+    probs = [inputs.blob_2d(n, 12044779, k) for k, n in enumerate((40, 72, 33))]
+    specs = [spec_of(p) for p in probs]
+    b = gpu_solver(specs, "f64", dict(tile=(16, 16), lds=1, fuse=1, persistent=1), [p.U for p in probs])
+    t, n = b.advance(0.01, 0.5, t0=[0.0, 0.0, 0.0])
+    for k, p in enumerate(probs):
+        ref, t_ref, n_ref = oracle.advance(oracle_mesh(p), p.U, 0.5, 0.01)
+        assert n[k] == n_ref and t[k] == t_ref
+        assert rel_err(gpu_state(b, k), ref) < 1e-11
+
+
+def test_set_variant_rejects_oversized_lds():
+    pr = inputs.random_state(3, (16, 16, 16), seed=1)
+    s = gpu_solver(spec_of(pr), "f64", None, pr.U)
+    with pytest.raises(pb.ParaisoError) as ei:
+        s.set_variant(dict(tile=(64, 64, 64), lds=1, fuse=1))
+    assert ei.value.code == pb.ERR_UNSUPPORTED
+    # the previous variant is still in place and works
+    s.step(1e-4)
