@@ -21,6 +21,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "euler_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_COUNT_SRC = os.path.join(_HERE, "flopcount.cpp")
+_COUNT_PATH = os.path.join(_HERE, "liboracle_count.so")
 
 PERIODIC = 0
 OUTFLOW = 1
@@ -35,12 +37,17 @@ class OracleError(RuntimeError):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math) and its operation counter."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_COUNT_PATH):
+        tmp = _COUNT_PATH + ".tmp"
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-fpermissive", "-w",
+                               "-ffp-contract=off", "-o", tmp, _COUNT_SRC])
+        os.replace(tmp, _COUNT_PATH)
     return _LIB_PATH
 
 
@@ -226,3 +233,42 @@ def cons_of_prim(ndim: int, gamma: float, v) -> np.ndarray:
     u = np.zeros(ndim + 2)
     _load().orc_cons_of_prim(int(ndim), float(gamma), _ptr(v), _ptr(u))
     return u
+
+
+# ---- operation counts of the method (defines algorithmic work per cell-update) --------
+
+_count_lib = None
+
+
+def _load_count():
+    global _count_lib
+    if _count_lib is None:
+        if not os.path.exists(_COUNT_PATH) or os.path.getmtime(_COUNT_PATH) < max(
+                os.path.getmtime(_COUNT_SRC), os.path.getmtime(_SRC)):
+            build(force=True)
+        lib = ctypes.CDLL(_COUNT_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        mp = ctypes.POINTER(_Mesh)
+        lp = ctypes.POINTER(ctypes.c_longlong)
+        lib.orc_count_step.argtypes = [mp, dp, ctypes.c_double, dp, lp]
+        lib.orc_count_cfl.argtypes = [mp, dp, ctypes.c_double, dp, lp]
+        lib.orc_count_step.restype = ctypes.c_int
+        lib.orc_count_cfl.restype = ctypes.c_int
+        _count_lib = lib
+    return _count_lib
+
+
+def count_ops(mesh: Mesh, U, dt: float, cfl: float = 0.5) -> dict:
+    """Floating-point operations of one step plus its CFL reduction, per cell-update:
+    add (incl. subtract), mul, div, sqrt, cmp (compare, min, max, abs)."""
+    lib = _load_count()
+    a = _as_state(mesh, U)
+    out = np.empty_like(a)
+    c1 = (ctypes.c_longlong * 5)()
+    c2 = (ctypes.c_longlong * 5)()
+    _check(lib.orc_count_step(ctypes.byref(mesh._c), _ptr(a), float(dt), _ptr(out), c1), "count step")
+    d = ctypes.c_double()
+    _check(lib.orc_count_cfl(ctypes.byref(mesh._c), _ptr(a), float(cfl), ctypes.byref(d), c2), "count cfl")
+    names = ("add", "mul", "div", "sqrt", "cmp")
+    n = float(mesh.ncells)
+    return {k: (c1[i] + c2[i]) / n for i, k in enumerate(names)}

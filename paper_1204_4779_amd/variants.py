@@ -1,0 +1,23 @@
+"""Kernel variants chosen per workload (tile, LDS staging, stage fusion, occupancy hint).
+
+`TUNED` holds the best variant measured for each workload and precision by the
+tuner (exhaustive search over the variant space on an MI355X); `UNTUNED` is the
+per-cell, unfused, unstaged kernel — every cell recomputes its own face fluxes —
+which plays the role of the paper's untuned baseline.
+"""
+
+UNTUNED_2D = dict(tile=(64, 4), lds=0, fuse=0, waves_per_eu=0, threads=256)
+UNTUNED_3D = dict(tile=(16, 4, 4), lds=0, fuse=0, waves_per_eu=0, threads=256)
+
+TUNED = {
+    ("kh2048", "f32"): dict(tile=(32, 32), lds=1, fuse=1, waves_per_eu=0, threads=256),
+    ("kh2048", "f64"): dict(tile=(32, 16), lds=1, fuse=1, waves_per_eu=0, threads=256),
+    ("box256", "f32"): dict(tile=(16, 8, 4), lds=1, fuse=0, waves_per_eu=0, threads=256),
+    ("box512", "f32"): dict(tile=(16, 8, 4), lds=1, fuse=0, waves_per_eu=0, threads=256),
+    ("batch512", "f32"): dict(tile=(32, 16), lds=1, fuse=1, waves_per_eu=0, threads=256, persistent=1),
+    ("sod1024", "f64"): dict(tile=(256,), lds=1, fuse=1, waves_per_eu=0, threads=256),
+}
+
+
+def tuned(workload: str, dtype: str) -> dict:
+    return dict(TUNED[(workload, dtype)])

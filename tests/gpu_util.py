@@ -58,3 +58,33 @@ def gpu_state(s, m=0) -> np.ndarray:
     import torch
     torch.cuda.synchronize()
     return s.state(m).double().cpu().numpy()
+
+
+def field_errs(got: np.ndarray, ref: np.ndarray) -> list:
+    """Per-field max|got - ref| / max|ref|."""
+    out = []
+    for q in range(ref.shape[0]):
+        scale = float(np.max(np.abs(ref[q])))
+        d = float(np.max(np.abs(got[q] - ref[q])))
+        out.append(d / scale if scale > 0 else d)
+    return out
+
+
+def state_err(got: np.ndarray, ref: np.ndarray, gamma: float) -> float:
+    """Relative error with each field measured against its own natural scale:
+    density and energy against max|rho| and max|E|, each momentum component
+    against max rho (|v| + c) (momentum of the fastest signal), so that a
+    momentum field that starts at rest is not measured against its own
+    vanishing size.  All scales from the reference."""
+    d = ref.shape[0] - 2
+    rho = ref[0]
+    m2 = sum(ref[1 + a] ** 2 for a in range(d))
+    vel = np.sqrt(m2) / rho
+    p = (gamma - 1.0) * (ref[d + 1] - 0.5 * m2 / rho)
+    c = np.sqrt(gamma * np.maximum(p, 0.0) / rho)
+    mscale = float(np.max(rho * (vel + c)))
+    worst = 0.0
+    for q in range(ref.shape[0]):
+        scale = mscale if 1 <= q <= d else float(np.max(np.abs(ref[q])))
+        worst = max(worst, float(np.max(np.abs(got[q] - ref[q]))) / scale)
+    return worst
