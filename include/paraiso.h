@@ -89,9 +89,10 @@ typedef struct paraiso_mesh {
  *   fuse         1: both Runge-Kutta stages in one launch, stage 1
  *                recomputed on a halo of 2 cells; 0: one launch per stage,
  *                stage-1 state kept in the workspace;
- *   waves_per_eu 0 (compiler's choice), 1, 2 or 4: occupancy hint that
- *                bounds registers per lane;
- *   threads      workgroup size, a multiple of 64 in [64, 1024], or 0 for
+ *   waves_per_eu 0 (compiler's choice, at most 256 VGPRs), 3, 4 or 5:
+ *                minimum waves per SIMD the kernel is compiled for, which
+ *                caps registers per lane at 168, 128 or 100;
+ *   threads      workgroup size, a multiple of 64 in [64, 512], or 0 for
  *                the default of the chosen kernel.
  */
 typedef struct paraiso_variant {
@@ -185,6 +186,43 @@ const char* paraiso_last_error(void);
 
 /* Library version string. */
 const char* paraiso_version(void);
+
+/* ------------------------------------------------------------------------
+ * Cost model of the kernel tuner: a multilayer perceptron in -> H -> H -> 1
+ * with ReLU hidden layers, trained with mean-squared error and Adam.  It
+ * predicts a variant's benchmark score from its features before the variant
+ * is benchmarked (the paper lists such prediction as future work for its
+ * tuner, section "Conclusion and Discussion").
+ *
+ * Parameters: one packed FP32 device array W1[in][H], b1[H], W2[H][H],
+ * b2[H], w3[H], b3 (row-major, input index first).  X is a device array
+ * [batch][in] (row-major).  All pointers are device pointers owned by the
+ * caller; the workspace holds activations.  Calls are asynchronous on
+ * `hip_stream` and bitwise reproducible (fixed-order reductions).
+ * Errors: INVALID_ARG (null pointer, batch/in/H < 1, in > 4096, H > 1024),
+ * WORKSPACE, HIP.
+ * ---------------------------------------------------------------------- */
+
+/* Number of parameters and workspace bytes for a batch size. */
+int32_t paraiso_mlp_sizes(int32_t in_dim, int32_t hidden, int32_t batch, int64_t* n_params,
+                          size_t* workspace_bytes);
+
+/* y[b] = network output for X[b]. */
+int32_t paraiso_mlp_forward(const float* X, int32_t batch, int32_t in_dim, int32_t hidden,
+                            const float* params, float* y, void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+
+/* loss = mean_b (y[b] - target[b])^2 (device scalar; may be NULL) and its
+ * gradient with respect to every parameter, packed like the parameters. */
+int32_t paraiso_mlp_loss_grad(const float* X, const float* target, int32_t batch, int32_t in_dim,
+                              int32_t hidden, const float* params, float* grad, float* loss,
+                              void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* One Adam update (Kingma & Ba) of n parameters in place; step >= 1 is the
+ * 1-based update count used for bias correction; m and v are the moment
+ * buffers (zero before the first step). */
+int32_t paraiso_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t n, float lr,
+                         float beta1, float beta2, float eps, int32_t step, void* hip_stream);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,8 @@ F64 = 1
 EXPORTS = ("paraiso_workspace_bytes", "paraiso_init", "paraiso_set_variant", "paraiso_get_variant",
            "paraiso_default_variant", "paraiso_cfl_dt", "paraiso_step", "paraiso_advance",
            "paraiso_current", "paraiso_totals", "paraiso_destroy", "paraiso_last_error",
-           "paraiso_version")
+           "paraiso_version", "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
+           "paraiso_mlp_adam")
 
 
 class ParaisoError(RuntimeError):
@@ -100,6 +101,11 @@ def load(path: str | None = None):
         "paraiso_destroy": ([vp], i32),
         "paraiso_last_error": ([], ctypes.c_char_p),
         "paraiso_version": ([], ctypes.c_char_p),
+        "paraiso_mlp_sizes": ([i32, i32, i32, ctypes.POINTER(i64), ctypes.POINTER(szt)], i32),
+        "paraiso_mlp_forward": ([vp, i32, i32, i32, vp, vp, vp, szt, vp], i32),
+        "paraiso_mlp_loss_grad": ([vp, vp, i32, i32, i32, vp, vp, vp, vp, szt, vp], i32),
+        "paraiso_mlp_adam": ([vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -191,6 +197,28 @@ def paraiso_destroy(ctx: int) -> None:
 
 def paraiso_version() -> str:
     return load().paraiso_version().decode()
+
+
+def paraiso_mlp_sizes(in_dim: int, hidden: int, batch: int) -> tuple:
+    n = ctypes.c_int64()
+    ws = ctypes.c_size_t()
+    _check(load().paraiso_mlp_sizes(in_dim, hidden, batch, ctypes.byref(n), ctypes.byref(ws)))
+    return n.value, ws.value
+
+
+def paraiso_mlp_forward(X_ptr, batch, in_dim, hidden, params_ptr, y_ptr, ws_ptr, ws_bytes, stream_ptr):
+    _check(load().paraiso_mlp_forward(X_ptr, batch, in_dim, hidden, params_ptr, y_ptr, ws_ptr, ws_bytes,
+                                      stream_ptr))
+
+
+def paraiso_mlp_loss_grad(X_ptr, T_ptr, batch, in_dim, hidden, params_ptr, grad_ptr, loss_ptr, ws_ptr, ws_bytes,
+                          stream_ptr):
+    _check(load().paraiso_mlp_loss_grad(X_ptr, T_ptr, batch, in_dim, hidden, params_ptr, grad_ptr, loss_ptr,
+                                        ws_ptr, ws_bytes, stream_ptr))
+
+
+def paraiso_mlp_adam(p_ptr, g_ptr, m_ptr, v_ptr, n, lr, beta1, beta2, eps, step, stream_ptr):
+    _check(load().paraiso_mlp_adam(p_ptr, g_ptr, m_ptr, v_ptr, n, lr, beta1, beta2, eps, step, stream_ptr))
 
 
 # --- torch-side convenience ----------------------------------------------------------------

@@ -35,6 +35,7 @@ struct MeshDev {
   double dx[3];
   double inv_dx[3];
   double gamma;
+  double inv_gm1;          // 1 / (gamma - 1)
   double vol;              // cell volume
 };
 
@@ -231,11 +232,11 @@ __device__ __forceinline__ Fields<T, D> fields(void* const* p) {
 }
 
 template <typename T>
-__device__ __forceinline__ Gas<T> gas_of(double gamma) {
+__device__ __forceinline__ Gas<T> gas_of(const MeshDev& M) {
   Gas<T> g;
-  g.gamma = (T)gamma;
-  g.gm1 = (T)(gamma - 1.0);
-  g.inv_gm1 = (T)(1.0 / (gamma - 1.0));
+  g.gamma = (T)M.gamma;
+  g.gm1 = (T)(M.gamma - 1.0);
+  g.inv_gm1 = (T)M.inv_gm1;
   return g;
 }
 
@@ -364,11 +365,11 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_direct(Args
     bool active;
     const double dt = step_dt(a, t.m, active);
     if (a.stage == 2 && t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
-    const Gas<T> g = gas_of<T>(M.gamma);
+    const Gas<T> g = gas_of<T>(M);
     const double cdt = (a.stage == 1 ? 0.5 : 1.0) * dt;
     T coef[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) coef[ax] = (T)(cdt / M.dx[ax]);
+    for (int ax = 0; ax < 3; ++ax) coef[ax] = (T)(cdt * M.inv_dx[ax]);
     const Fields<T, D> U0 = fields<T, D>(M.s[a.src]);
     const Fields<T, D> Uin = a.stage == 1 ? U0 : fields<T, D>(M.w);
     const Fields<T, D> Uout = a.stage == 1 ? fields<T, D>(M.w) : fields<T, D>(M.s[1 - a.src]);
@@ -459,12 +460,12 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_direct(Args
     bool active;
     const double dt = step_dt(a, t.m, active);
     if (t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
-    const Gas<T> g = gas_of<T>(M.gamma);
+    const Gas<T> g = gas_of<T>(M);
     T coef1[3], coef2[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      coef1[ax] = (T)((0.5 * dt) / M.dx[ax]);
-      coef2[ax] = (T)(dt / M.dx[ax]);
+      coef1[ax] = (T)((0.5 * dt) * M.inv_dx[ax]);
+      coef2[ax] = (T)(dt * M.inv_dx[ax]);
     }
     const Fields<T, D> U0 = fields<T, D>(M.s[a.src]);
     const Fields<T, D> Uout = fields<T, D>(M.s[1 - a.src]);
@@ -610,11 +611,11 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
     const double dt = step_dt(a, t.m, active);
     if (a.stage == 2 && t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
     if (!active && a.stage == 1) continue;
-    const Gas<T> g = gas_of<T>(M.gamma);
+    const Gas<T> g = gas_of<T>(M);
     const double cdt = (a.stage == 1 ? 0.5 : 1.0) * dt;
     T coef[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) coef[ax] = (T)(cdt / M.dx[ax]);
+    for (int ax = 0; ax < 3; ++ax) coef[ax] = (T)(cdt * M.inv_dx[ax]);
     const Fields<T, D> U0 = fields<T, D>(M.s[a.src]);
     const Fields<T, D> Uin = a.stage == 1 ? U0 : fields<T, D>(M.w);
     const Fields<T, D> Uout = a.stage == 1 ? fields<T, D>(M.w) : fields<T, D>(M.s[1 - a.src]);
@@ -676,12 +677,12 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_lds(Args a,
     bool active;
     const double dt = step_dt(a, t.m, active);
     if (t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
-    const Gas<T> g = gas_of<T>(M.gamma);
+    const Gas<T> g = gas_of<T>(M);
     T coef1[3], coef2[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      coef1[ax] = (T)((0.5 * dt) / M.dx[ax]);
-      coef2[ax] = (T)(dt / M.dx[ax]);
+      coef1[ax] = (T)((0.5 * dt) * M.inv_dx[ax]);
+      coef2[ax] = (T)(dt * M.inv_dx[ax]);
     }
     const Fields<T, D> U0 = fields<T, D>(M.s[a.src]);
     const Fields<T, D> Uout = fields<T, D>(M.s[1 - a.src]);

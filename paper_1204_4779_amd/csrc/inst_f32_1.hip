@@ -4,8 +4,8 @@
 
 namespace paraiso {
 
-#define PARAISO_SET(K) {(const void*)K<float, 1, 0>, (const void*)K<float, 1, 1>, \
-                        (const void*)K<float, 1, 2>, (const void*)K<float, 1, 4>}
+#define PARAISO_SET(K) {(const void*)K<float, 1, 0>, (const void*)K<float, 1, 3>, \
+                        (const void*)K<float, 1, 4>, (const void*)K<float, 1, 5>}
 
 const KernelTable* table_f32_1() {
   static const KernelTable t = {

@@ -4,8 +4,8 @@
 
 namespace paraiso {
 
-#define PARAISO_SET(K) {(const void*)K<float, 3, 0>, (const void*)K<float, 3, 1>, \
-                        (const void*)K<float, 3, 2>, (const void*)K<float, 3, 4>}
+#define PARAISO_SET(K) {(const void*)K<float, 3, 0>, (const void*)K<float, 3, 3>, \
+                        (const void*)K<float, 3, 4>, (const void*)K<float, 3, 5>}
 
 const KernelTable* table_f32_3() {
   static const KernelTable t = {

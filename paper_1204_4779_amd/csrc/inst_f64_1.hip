@@ -4,8 +4,8 @@
 
 namespace paraiso {
 
-#define PARAISO_SET(K) {(const void*)K<double, 1, 0>, (const void*)K<double, 1, 1>, \
-                        (const void*)K<double, 1, 2>, (const void*)K<double, 1, 4>}
+#define PARAISO_SET(K) {(const void*)K<double, 1, 0>, (const void*)K<double, 1, 3>, \
+                        (const void*)K<double, 1, 4>, (const void*)K<double, 1, 5>}
 
 const KernelTable* table_f64_1() {
   static const KernelTable t = {

@@ -4,8 +4,8 @@
 
 namespace paraiso {
 
-#define PARAISO_SET(K) {(const void*)K<double, 2, 0>, (const void*)K<double, 2, 1>, \
-                        (const void*)K<double, 2, 2>, (const void*)K<double, 2, 4>}
+#define PARAISO_SET(K) {(const void*)K<double, 2, 0>, (const void*)K<double, 2, 3>, \
+                        (const void*)K<double, 2, 4>, (const void*)K<double, 2, 5>}
 
 const KernelTable* table_f64_2() {
   static const KernelTable t = {

@@ -4,8 +4,8 @@
 
 namespace paraiso {
 
-#define PARAISO_SET(K) {(const void*)K<double, 3, 0>, (const void*)K<double, 3, 1>, \
-                        (const void*)K<double, 3, 2>, (const void*)K<double, 3, 4>}
+#define PARAISO_SET(K) {(const void*)K<double, 3, 0>, (const void*)K<double, 3, 3>, \
+                        (const void*)K<double, 3, 4>, (const void*)K<double, 3, 5>}
 
 const KernelTable* table_f64_3() {
   static const KernelTable t = {

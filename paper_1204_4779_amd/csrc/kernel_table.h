@@ -3,8 +3,8 @@
 
 namespace paraiso {
 
-// index of a waves-per-EU hint in the tables: 0 (compiler), 1, 2, 4
-inline int waves_slot(int w) { return w == 1 ? 1 : (w == 2 ? 2 : (w == 4 ? 3 : 0)); }
+// index of a waves-per-EU hint in the tables: 0 (compiler), 3, 4, 5
+inline int waves_slot(int w) { return w == 3 ? 1 : (w == 4 ? 2 : (w == 5 ? 3 : 0)); }
 
 struct KernelTable {
   const void* stage_direct[4];

@@ -20,8 +20,12 @@
 using namespace paraiso;
 
 namespace {
-
 thread_local std::string g_err;
+}
+
+void paraiso_set_error(const std::string& msg) { g_err = msg; }
+
+namespace {
 
 int fail(int code, const std::string& msg) {
   g_err = msg;
@@ -305,12 +309,12 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   if (v.lds != 0 && v.lds != 1) return why = "lds must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (v.fuse != 0 && v.fuse != 1) return why = "fuse must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
-  if (!(v.waves_per_eu == 0 || v.waves_per_eu == 1 || v.waves_per_eu == 2 || v.waves_per_eu == 4))
-    return why = "waves_per_eu must be 0, 1, 2 or 4", PARAISO_ERR_UNSUPPORTED;
+  if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
+    return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
   if (v.threads != 0 && (v.threads < 64 || v.threads > 512 || v.threads % 64))
     return why = "threads must be 0 or a multiple of 64 in [64, 512]", PARAISO_ERR_UNSUPPORTED;
   const int64_t tc = (int64_t)v.tile[0] * v.tile[1] * v.tile[2];
-  if (tc > 65536) return why = "tile has more than 65536 cells", PARAISO_ERR_UNSUPPORTED;
+  if (tc > (1 << 22)) return why = "tile has more than 2^22 cells", PARAISO_ERR_UNSUPPORTED;
   return PARAISO_OK;
 }
 
@@ -529,6 +533,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
       if (a < pm.ndim) vol *= pm.dx[a];
     }
     M.gamma = pm.gamma;
+    M.inv_gm1 = 1.0 / (pm.gamma - 1.0);
     M.vol = vol;
     M.ncells = (int)cells_of(pm);
     M.chunk0 = chunk;

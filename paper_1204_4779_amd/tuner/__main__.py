@@ -1,0 +1,99 @@
+"""Tuner command line.
+
+    python -m paper_1204_4779_amd.tuner measure --workload box512 --db DB.jsonl
+        benchmark every statically valid variant on the GPU (resumes a partial DB)
+    python -m paper_1204_4779_amd.tuner gain --db DB.jsonl [--seeds 9] [--frac 0.1]
+        replay the database: MLP-guided vs random vs PAGSA search at the same budget
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from . import measure, search
+from . import space as sp
+from .db import DB
+
+
+def log(msg: str):
+    print(msg, flush=True)
+
+
+def cmd_measure(a):
+    wl = measure.WORKLOADS[a.workload]
+    db = DB(a.db)
+    cands = search.candidates(wl.ndim, wl.esize)
+    log(f"{wl.name}: {len(sp.enumerate_space(wl.ndim))} raw variants, {len(cands)} statically valid, "
+        f"{sum(1 for v in cands if sp.key(v) in db)} already in the database")
+    bench = measure.Bench(wl, log=log)
+    ev = search.LiveEvaluator(bench, db, wl.ndim, log=log)
+    # fast families first so the screening threshold is set early
+    order = sorted(cands, key=lambda v: (-v["lds"], v["fuse"] and not v["lds"]))
+    for v in order:
+        ev(v)
+    best = db.best()
+    log(f"best: {best['key']} {best['mu'] / 1e9:.3f} Gcups; total benchmark cost {db.total_cost():.1f} s")
+    bench.close()
+
+
+def gain_study(db: DB, ndim: int, esize: int, seeds: int = 9, frac: float = 0.1, log=log) -> dict:
+    cands = search.candidates(ndim, esize)
+    ev = search.ReplayEvaluator(db)
+    truth = search.exhaustive(cands, ev)
+    budget = frac * truth.spent
+    out = {"optimum_key": truth.best_key, "optimum_mu": truth.best_mu, "exhaustive_cost": truth.spent,
+           "budget": budget, "runs": {}}
+    for name in ("mlp", "random", "pagsa"):
+        res = []
+        for s in range(seeds):
+            rng = np.random.default_rng(1000 + s)
+            if name == "mlp":
+                tr = search.mlp_guided(cands, ev, budget, rng, ndim, esize, model_seed=s)
+            elif name == "random":
+                tr = search.random_search(cands, ev, budget, rng)
+            else:
+                seedv = [cands[int(i)] for i in rng.permutation(len(cands))[:8]]
+                tr = search.pagsa(cands, ev, budget, rng, ndim, seedv)
+            res.append({"seed": s, "best_frac": tr.best_mu / truth.best_mu, "best_key": tr.best_key,
+                        "spent": tr.spent, "evaluated": len(tr.evaluated)})
+            log(f"{name} seed {s}: best {tr.best_mu / truth.best_mu:.4f} of optimum after "
+                f"{len(tr.evaluated)} benchmarks, {tr.spent:.1f} s")
+        out["runs"][name] = res
+        out[f"{name}_median"] = float(np.median([r["best_frac"] for r in res]))
+    return out
+
+
+def cmd_gain(a):
+    db = DB(a.db)
+    wl = measure.WORKLOADS[a.workload]
+    out = gain_study(db, wl.ndim, wl.esize, a.seeds, a.frac)
+    log(json.dumps({k: v for k, v in out.items() if k != "runs"}))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="paper_1204_4779_amd.tuner")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    m = sub.add_parser("measure")
+    m.add_argument("--workload", default="box512", choices=sorted(measure.WORKLOADS))
+    m.add_argument("--db", required=True)
+    g = sub.add_parser("gain")
+    g.add_argument("--workload", default="box512", choices=sorted(measure.WORKLOADS))
+    g.add_argument("--db", required=True)
+    g.add_argument("--seeds", type=int, default=9)
+    g.add_argument("--frac", type=float, default=0.1)
+    g.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "measure":
+        cmd_measure(a)
+    else:
+        cmd_gain(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,135 @@
+"""Variant space, genome encoding and features.
+
+A variant is (tile per axis, LDS staging, RK-stage fusion, waves-per-EU hint).
+The genome is its bit string: 2 bits per active axis for the tile
+(8, 16, 32, 64), one bit each for LDS and fusion, 2 bits for the hint
+(0 = compiler's choice, 3, 4, 5).  The paper's genome encodes Manifest /
+Delayed choices and launch configurations of generated code ("Tuning
+Targets"); here LDS staging and stage fusion are the storage-versus-recompute
+choices and tile and occupancy hint are the launch configuration.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+TILE_VALUES = (8, 16, 32, 64)
+WAVE_VALUES = (0, 3, 4, 5)
+KMAXR = 8                  # cells per thread the LDS kernels keep in registers
+MAX_LDS_BYTES = 160 * 1024  # per workgroup on gfx950
+STATIC_LDS = 16 * 8 + 64
+
+
+def threads_for(variant: dict, ndim: int) -> int:
+    """Workgroup size: 256, or 512 when an LDS tile needs more than KMAXR cells per thread."""
+    if not variant["lds"]:
+        return 256
+    c1 = region(variant, ndim, 2 if variant["fuse"] else 0)
+    tile = region(variant, ndim, 0)
+    for t in (256, 512):
+        if max(c1, tile) <= KMAXR * t:
+            return t
+    return 512
+
+
+def region(variant: dict, ndim: int, halo: int) -> int:
+    n = 1
+    for a in range(ndim):
+        n *= variant["tile"][a] + 2 * halo
+    return n
+
+
+def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
+    """Dynamic LDS of the LDS kernels: primitive region plus the largest face-flux block."""
+    t = list(variant["tile"][:ndim])
+    H = 4 if variant["fuse"] else 2
+    vin = 1
+    for a in range(ndim):
+        vin *= t[a] + 2 * H
+    c1 = [x + 4 for x in t] if variant["fuse"] else t
+    fmax = 0
+    for a in range(ndim):
+        f1 = 1
+        f2 = 1
+        for b in range(ndim):
+            f1 *= c1[b] + (1 if b == a else 0)
+            f2 *= t[b] + (1 if b == a else 0)
+        fmax = max(fmax, f1, f2)
+    return esize * (ndim + 2) * (vin + fmax)
+
+
+def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
+    if not variant["lds"]:
+        return True
+    if lds_bytes(variant, ndim, esize) + STATIC_LDS > MAX_LDS_BYTES:
+        return False
+    c1 = region(variant, ndim, 2 if variant["fuse"] else 0)
+    return max(c1, region(variant, ndim, 0)) <= KMAXR * threads_for(variant, ndim)
+
+
+def make_variant(tile, lds, fuse, waves, ndim) -> dict:
+    t = tuple(tile) + (1,) * (3 - len(tile))
+    v = {"tile": t, "lds": int(lds), "fuse": int(fuse), "waves_per_eu": int(waves)}
+    v["threads"] = threads_for(v, ndim)
+    return v
+
+
+def enumerate_space(ndim: int) -> list:
+    out = []
+    for tile in itertools.product(TILE_VALUES, repeat=ndim):
+        for lds in (0, 1):
+            for fuse in (0, 1):
+                for w in WAVE_VALUES:
+                    out.append(make_variant(tile, lds, fuse, w, ndim))
+    return out
+
+
+def key(variant: dict) -> str:
+    t = variant["tile"]
+    return f"t{t[0]}x{t[1]}x{t[2]}_l{variant['lds']}_f{variant['fuse']}_w{variant['waves_per_eu']}"
+
+
+# ---- genome -------------------------------------------------------------------------------
+
+def genome_bits(ndim: int) -> int:
+    return 2 * ndim + 4
+
+
+def encode(variant: dict, ndim: int) -> str:
+    bits = []
+    for a in range(ndim):
+        i = TILE_VALUES.index(variant["tile"][a])
+        bits += [(i >> 1) & 1, i & 1]
+    bits += [variant["lds"], variant["fuse"]]
+    w = WAVE_VALUES.index(variant["waves_per_eu"])
+    bits += [(w >> 1) & 1, w & 1]
+    return "".join(str(b) for b in bits)
+
+
+def decode(genome: str, ndim: int) -> dict:
+    b = [int(c) for c in genome]
+    if len(b) != genome_bits(ndim):
+        raise ValueError("genome length")
+    tile = [TILE_VALUES[b[2 * a] * 2 + b[2 * a + 1]] for a in range(ndim)]
+    o = 2 * ndim
+    return make_variant(tile, b[o], b[o + 1], WAVE_VALUES[b[o + 2] * 2 + b[o + 3]], ndim)
+
+
+# ---- features of the cost model ---------------------------------------------------------
+
+def features(variant: dict, ndim: int, esize: int) -> list:
+    t = variant["tile"]
+    cells = region(variant, ndim, 0)
+    halo = region(variant, ndim, 2 if variant["fuse"] else 0) / cells
+    loads = region(variant, ndim, 4 if variant["fuse"] else 2) / cells
+    w = variant["waves_per_eu"]
+    f = [math.log2(t[a]) / 6.0 for a in range(3)]
+    f += [float(variant["lds"]), float(variant["fuse"]), float(variant["lds"] * variant["fuse"])]
+    f += [1.0 if w == x else 0.0 for x in WAVE_VALUES]
+    f += [math.log2(cells) / 18.0, halo / 4.0, math.log2(loads) / 4.0,
+          lds_bytes(variant, ndim, esize) / MAX_LDS_BYTES if variant["lds"] else 0.0,
+          variant["threads"] / 512.0]
+    return f
+
+
+N_FEATURES = 16

@@ -57,7 +57,7 @@ def test_smooth_2d_many_tiles_and_persistent(dtype):
     ref = oracle.step(m, U0, dt)
     for v in (dict(tile=(32, 16), lds=1, fuse=1, persistent=1),
               dict(tile=(16, 16), lds=1, fuse=0, persistent=1, threads=128),
-              dict(tile=(64, 8), lds=1, fuse=1, waves_per_eu=2, threads=512)):
+              dict(tile=(64, 8), lds=1, fuse=1, waves_per_eu=4, threads=512)):
         s = gpu_solver(spec_of(pr), dtype, v, pr.U)
         s.step(dt)
         assert rel_err(gpu_state(s), ref) <= TOL[dtype], v

@@ -1,0 +1,149 @@
+"""Tuner logic without a GPU: genome codec, the paper's birth operators and draw rule,
+budgets, database resume and failure handling (a broken variant scores 0)."""
+import json
+import math
+
+import numpy as np
+import pytest
+
+from paper_1204_4779_amd.tuner import search
+from paper_1204_4779_amd.tuner import space as sp
+from paper_1204_4779_amd.tuner.db import DB
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_genome_round_trip(ndim):
+    seen = set()
+    for v in sp.enumerate_space(ndim):
+        g = sp.encode(v, ndim)
+        assert len(g) == sp.genome_bits(ndim)
+        assert sp.decode(g, ndim) == v
+        seen.add(g)
+    assert len(seen) == 4 ** ndim * 16
+
+
+def test_triangulation_table():
+    # Base / Secondary / Primary -> Child, the paper's binary operation table
+    table = {("0", "0", "0"): "0", ("0", "0", "1"): "1", ("0", "1", "0"): "1", ("0", "1", "1"): "1",
+             ("1", "0", "0"): "0", ("1", "0", "1"): "0", ("1", "1", "0"): "0", ("1", "1", "1"): "1"}
+    for (b, s, p), c in table.items():
+        assert search.triangulate(b, s, p) == c
+    assert search.triangulate("0011", "0101", "1001") == "1101"
+
+
+def test_draw_weights_temperature():
+    mus = np.array([10.0, 9.0, 5.0, 1.0])
+    sig = np.array([0.1, 0.1, 0.1, 0.1])
+    cold = search.draw_weights(mus, sig, 1e-3)
+    hot = search.draw_weights(mus, sig, 1e6)
+    assert cold[0] > 0.99                      # low temperature: the best individual
+    assert np.all(np.abs(hot - 0.25) < 1e-3)   # high temperature: score hardly matters
+    # differences small against the deviations are ignored
+    even = search.draw_weights(np.array([10.0, 9.99]), np.array([1.0, 1.0]), 1e-3)
+    assert abs(even[0] - even[1]) < 0.01
+    assert np.all(np.diff(search.draw_weights(mus, sig, 2.0)) <= 0)
+
+
+def test_temperature_range():
+    rng = np.random.default_rng(0)
+    mus, sig = np.array([100.0, 50.0]), np.array([2.0, 1.0])
+    Ts = [search.draw_temperature(mus, sig, rng) for _ in range(2000)]
+    assert min(Ts) >= 2.0 - 1e-9 and max(Ts) <= 100.0 + 1e-9
+    logs = np.log(Ts)
+    # log-uniform: mean of log T at the midpoint
+    assert abs(np.mean(logs) - 0.5 * (math.log(2.0) + math.log(100.0))) < 0.1
+
+
+def test_mutation_and_crossover_change_or_mix():
+    rng = np.random.default_rng(1)
+    g = "0101010101"
+    for _ in range(100):
+        assert search.mutate(g, rng) != g
+        c = search.crossover("0000000000", "1111111111", rng)
+        assert len(c) == 10 and set(c) <= {"0", "1"}
+
+
+def _synthetic_db(ndim=3, esize=4, seed=3, broken=None):
+    """A fake measured database: speed a smooth function of the features plus noise."""
+    rng = np.random.default_rng(seed)
+    db = DB()
+    for v in sp.enumerate_space(ndim):
+        k = sp.key(v)
+        ok = sp.statically_valid(v, ndim, esize)
+        t = v["tile"]
+        mu = 0.0
+        if ok:
+            mu = 1e9 * (1 + 3 * v["lds"]) * (1 + 0.5 * v["fuse"] * v["lds"]) / (1 + 4 * v["fuse"] * (1 - v["lds"]))
+            mu *= math.exp(-0.3 * abs(math.log2(t[0]) - 4) - 0.2 * abs(math.log2(t[1]) - 3))
+            mu *= 1 + 0.05 * rng.normal()
+        valid = ok and k != broken
+        db.add({"key": k, "genome": sp.encode(v, ndim), "variant": v, "valid": valid,
+                "mu": mu if valid else 0.0, "sigma": 0.01 * mu, "cost": 1.0 + (5.0 if not v["lds"] else 0.0)})
+    return db
+
+
+def test_budget_and_determinism():
+    db = _synthetic_db()
+    cands = search.candidates(3, 4)
+    ev = search.ReplayEvaluator(db)
+    a = search.random_search(cands, ev, 60.0, np.random.default_rng(5))
+    b = search.random_search(cands, ev, 60.0, np.random.default_rng(5))
+    assert a.evaluated == b.evaluated
+    assert a.spent - a.evaluated[-1][2] < 60.0
+    p = search.pagsa(cands, ev, 60.0, np.random.default_rng(7), 3, cands[:8])
+    keys = [k for k, _, _ in p.evaluated]
+    assert len(keys) == len(set(keys))          # every child is a new genome
+    assert p.spent - p.evaluated[-1][2] < 60.0
+
+
+def test_pagsa_improves_on_its_seeds():
+    db = _synthetic_db()
+    cands = search.candidates(3, 4)
+    ev = search.ReplayEvaluator(db)
+    rng = np.random.default_rng(11)
+    seeds = [cands[int(i)] for i in rng.permutation(len(cands))[:8]]
+    tr = search.pagsa(cands, ev, 200.0, rng, 3, seeds)
+    seed_best = max(ev(v)["mu"] for v in seeds)
+    assert tr.best_mu >= seed_best
+    births = {r for r in (k for k, _, _ in tr.evaluated)}
+    assert len(births) > 8
+
+
+def test_broken_variant_scores_zero_and_is_never_best():
+    cands = search.candidates(3, 4)
+    clean = _synthetic_db()
+    best = search.exhaustive(cands, search.ReplayEvaluator(clean)).best_key
+    db = _synthetic_db(broken=best)
+    tr = search.exhaustive(cands, search.ReplayEvaluator(db))
+    assert tr.best_key != best
+    assert dict((k, mu) for k, mu, _ in tr.evaluated)[best] == 0.0
+
+
+def test_db_resume_skips_measured(tmp_path):
+    path = str(tmp_path / "db.jsonl")
+    calls = []
+
+    class FakeBench:
+        def measure(self, v):
+            calls.append(sp.key(v))
+            return {"valid": True, "mu": 1e9, "sigma": 1e7, "cost": 0.5, "reason": "ok"}
+
+    cands = search.candidates(2, 4)[:10]
+    ev = search.LiveEvaluator(FakeBench(), DB(path), 2)
+    for v in cands[:6]:
+        ev(v)
+    # a forced stop: reopen the database and continue
+    ev2 = search.LiveEvaluator(FakeBench(), DB(path), 2)
+    for v in cands:
+        ev2(v)
+    assert calls == [sp.key(v) for v in cands[:6]] + [sp.key(v) for v in cands[6:]]
+    rows = [json.loads(l) for l in open(path)]
+    assert len(rows) == 10 and len({r["key"] for r in rows}) == 10
+
+
+def test_static_validity_examples():
+    big = sp.make_variant((64, 64, 64), 1, 1, 0, 3)
+    assert not sp.statically_valid(big, 3, 4)
+    ok = sp.make_variant((16, 8, 8), 1, 0, 0, 3)
+    assert sp.statically_valid(ok, 3, 4)
+    assert sp.statically_valid(sp.make_variant((64, 64, 64), 0, 1, 5, 3), 3, 4)
