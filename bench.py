@@ -44,15 +44,20 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes, each scaled by the reading of a plain 512 MiB device copy
 # (factors 2.000 and 1.000); valid only for the kernel sources they were taken
 # on (hash of the device headers) and the variant named.
-TRAFFIC = {"sources": "569ff4b8b5c7391a", "variant": {"tile": [32, 32], "lds": 1, "fuse": 1},
-           "bytes_per_launch": 137.1e6}
+TRAFFIC = {"sources": "9ce98fc80e2db3c8", "variant": {"tile": [64, 16], "lds": 2, "fuse": 1},
+           "bytes_per_launch": 167.0e6}
+
+
+KERNEL_NAME = {(2, 1): "k_march2d<float,0,true>", (2, 0): "k_march2d<float,0,false>",
+               (1, 1): "k_fused_lds<float,2>", (1, 0): "k_stage_lds<float,2>",
+               (0, 0): "k_stage_direct<float,2>", (0, 1): "k_fused_direct<float,2>"}
 
 
 def _kernel_source_hash() -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_1204_4779_amd", "csrc")
     digests = ""
-    for f in ("euler_device.h", "euler_kernels.h"):
+    for f in ("euler_device.h", "euler_kernels.h", "euler_march2d.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             digests += hashlib.sha256(fh.read()).hexdigest() + "\n"
     return hashlib.sha256(digests.encode()).hexdigest()[:16]
@@ -70,35 +75,46 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(U, dtype: str, variant: dict, steps: int, warmup: int):
+def run_gpu(U, dtype: str, variant: dict, steps: int, warmup: int, specs=None, t_end=float("inf")):
+    """Advance `steps` device-dt steps after `warmup`; U is one state or a list (batch)."""
     import torch
     from paper_1204_4779_amd import binding as pb
-    spec = pb.MeshSpec(2, (N, N), 1.4, (0, 0))
-    s = pb.Solver(spec, dtype)
+    if specs is None:
+        specs = [pb.MeshSpec(2, (N, N), 1.4, (0, 0))]
+    s = pb.Solver(specs, dtype)
     s.set_variant(variant)
     s.upload(U)
-    tot0 = s.totals()[0]
-    t = [0.0]
+    count = len(specs)
+    tot0 = s.totals()
+    t = [0.0] * count
     if warmup:
-        t, _ = s.advance(float("inf"), CFL, max_steps=warmup, t0=t)
+        t, _ = s.advance(t_end, CFL, max_steps=warmup, t0=t)
     stream = s.stream
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
     start.record(stream)
-    t, n = s.advance(float("inf"), CFL, max_steps=steps, t0=t)
+    t, n = s.advance(t_end, CFL, max_steps=steps, t0=t)
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ev_ms = start.elapsed_time(stop)
-    tot1 = s.totals()[0]
-    drift = max(abs(a - b) / max(abs(a), 1e-300) for a, b in zip(tot0, tot1) if abs(a) > 0)
+    tot1 = s.totals()
+    # conserved-total audit: mass and energy relative to themselves, momentum
+    # relative to the mass total (unit velocity scale)
+    drift = {"mass": 0.0, "momentum": 0.0, "energy": 0.0}
+    for a0, a1 in zip(tot0, tot1):
+        nf = len(a0)
+        drift["mass"] = max(drift["mass"], abs(a1[0] - a0[0]) / abs(a0[0]))
+        drift["energy"] = max(drift["energy"], abs(a1[-1] - a0[-1]) / abs(a0[-1]))
+        for q in range(1, nf - 1):
+            drift["momentum"] = max(drift["momentum"], abs(a1[q] - a0[q]) / abs(a0[0]))
     launches = steps * (1 if variant.get("fuse", 1) else 2)
     s.close()
     del s
     torch.cuda.empty_cache()
-    return {"wall_s": wall, "event_ms": ev_ms, "steps": n[0], "t": t[0], "launches": launches,
+    return {"wall_s": wall, "event_ms": ev_ms, "steps": n, "t": t, "launches": launches,
             "mass_energy_drift": drift}
 
 
@@ -121,6 +137,49 @@ def cpu_baseline(U, budget_s: float = 12.0):
             "sample": f"{steps} FP64 steps (+CFL) of the full 2048x2048 KH mesh, serial C, {el:.1f} s"}
 
 
+def other_workload(name: str, steps: int, warmup: int):
+    """Cell-updates/s of the other configurations (one JSON line each, not the headline)."""
+    from paper_1204_4779_amd import binding as pb
+    from paper_1204_4779_amd import inputs
+    if name == "sod1024":
+        pr = inputs.sod_1d(1024)
+        spec = pb.MeshSpec(1, pr.n, pr.gamma, pr.bc)
+        var = variants.tuned("sod1024", "f64")
+        r = run_gpu(pr.U, "f64", var, 1 << 30, 0, specs=[spec], t_end=0.2)
+        cells = 1024 * r["steps"][0]
+        return {"workload": "sod_1d_1024_outflow_fp64_to_t0.2", "value": cells / (r["event_ms"] / 1e3),
+                "unit": "cell-updates/s", "dtype": "f64", "steps": r["steps"][0], "t": r["t"][0],
+                "time_to_solution_ms": r["event_ms"], "variant": var}
+    if name in ("box256", "box512"):
+        n = 256 if name == "box256" else 512
+        import torch
+        spec = pb.MeshSpec(3, (n, n, n), 5.0 / 3.0, (0, 0, 0))
+        chunks = [inputs.turbulent_box_3d(n, seed=4779, z_range=(z, min(n, z + 32))).U for z in range(0, n, 32)]
+        import numpy as np
+        U = np.concatenate(chunks, axis=1)
+        var = variants.tuned(name, "f32")
+        r = run_gpu(U, "f32", var, steps, warmup, specs=[spec])
+        cells = n ** 3
+        v = cells * steps / (r["event_ms"] / 1e3)
+        return {"workload": f"box3d_{n}^3_periodic_fp32", "value": v, "unit": "cell-updates/s", "dtype": "f32",
+                "ms_per_step": r["event_ms"] / steps, "variant": var,
+                "hbm_frac": v * bytes_per_cell_update(3, 4) / 1e9 / HBM_PEAK_GBS,
+                "alu_frac": v * 1322.0 / 1e12 / ALU_PEAK_TFLOPS["f32"], "audit_drift": r["mass_energy_drift"]}
+    if name == "batch512":
+        probs = inputs.blob_batch(512, seed=12044779)
+        specs = [pb.MeshSpec(2, p.n, p.gamma, p.bc) for p in probs]
+        var = variants.tuned("batch512", "f32")
+        r = run_gpu([p.U for p in probs], "f32", var, steps, warmup, specs=specs)
+        cells = sum(p.n[0] * p.n[1] for p in probs)
+        v = cells * steps / (r["event_ms"] / 1e3)
+        return {"workload": "batch_512_uneven_2d_periodic_fp32", "value": v, "unit": "cell-updates/s",
+                "dtype": "f32", "cells": cells, "ms_per_step": r["event_ms"] / steps, "variant": var,
+                "hbm_frac": v * bytes_per_cell_update(2, 4) / 1e9 / HBM_PEAK_GBS,
+                "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS["f32"],
+                "audit_drift": r["mass_energy_drift"]}
+    raise SystemExit(f"unknown workload {name}")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +188,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="headline FP32 only")
     ap.add_argument("--variant", type=str, default=None, help="JSON variant for the headline run")
+    ap.add_argument("--workload", default="kh2048",
+                    choices=("kh2048", "sod1024", "box256", "box512", "batch512"),
+                    help="kh2048 is the headline; the others print their own line")
     ap.add_argument("--prof", action="store_true",
                     help="profiling run: headline only, plus a 512 MiB device copy that calibrates HBM counters")
     args = ap.parse_args()
@@ -146,6 +208,11 @@ def main():
         print(json.dumps({"error": "no GPU"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload != "kh2048":
+        out = other_workload(args.workload, args.steps, args.warmup)
+        out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "data": "synthetic"})
+        print(json.dumps(out))
+        return
     log("generating KH 2048^2 input")
     pr = inputs.kelvin_helmholtz_2d(N, seed=1204)
     cells = N * N
@@ -153,6 +220,7 @@ def main():
     tuned32 = json.loads(args.variant) if args.variant else TUNED["f32"]
     log(f"FP32 tuned {tuned32}")
     r32 = run_gpu(pr.U, "f32", tuned32, args.steps, args.warmup)
+    r32["steps"], r32["t"] = r32["steps"][0], r32["t"][0]
     ms = r32["event_ms"] / args.steps
     value = cells * args.steps / (r32["event_ms"] / 1e3)
 
@@ -166,7 +234,7 @@ def main():
         ru64 = run_gpu(pr.U, "f64", UNTUNED, max(args.steps // 4, 10), min(args.warmup, 5))
         for name, r, dt, var in (("f64_tuned", r64, "f64", TUNED["f64"]), ("f32_untuned", ru32, "f32", UNTUNED),
                                  ("f64_untuned", ru64, "f64", UNTUNED)):
-            k = r["steps"]
+            k = r["steps"][0]
             cups = cells * k / (r["event_ms"] / 1e3)
             esz = 4 if dt == "f32" else 8
             extra[name] = {"value": cups, "ms_per_step": r["event_ms"] / k, "variant": var,
@@ -187,7 +255,7 @@ def main():
         traffic = TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": ALU_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved_tf / ALU_PEAK_TFLOPS["f32"], 4), "traffic": traffic,
-                "kernel": "k_fused_lds<float,2>", "flops_per_launch": flops, "launch_ms": round(launch_ms, 5),
+                "kernel": KERNEL_NAME.get((tuned32.get("lds", 1), tuned32.get("fuse", 1)), "?"), "flops_per_launch": flops, "launch_ms": round(launch_ms, 5),
                 "peak_packed_f32": ALU_PEAK_PACKED_F32}
     hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_launch}
@@ -213,7 +281,8 @@ def main():
         "config": {"workload": "kelvin_helmholtz_2d_2048x2048_periodic_gamma1.4_seed1204", "cells": cells,
                    "cfl": CFL, "variant": tuned32, "hbm_frac": hbm["frac"]},
         "roofline": roofline, "hbm_roofline": hbm, "cpu_baseline": cpu, "extra": extra,
-        "audit": {"f32_total_rel_drift": r32["mass_energy_drift"], "t_end": r32["t"]},
+        "audit": {"f32_conserved_total_drift": r32["mass_energy_drift"], "steps": args.steps + args.warmup,
+                  "t_end": r32["t"]},
     }
     print(json.dumps(out))
 

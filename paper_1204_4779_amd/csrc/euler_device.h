@@ -57,16 +57,18 @@ struct Box {
   }
 };
 
-// Map a possibly out-of-range cell index onto the mesh along one axis.
+// Map any cell index onto [0, n) along one axis: clamp (outflow) or wrap
+// (periodic).  One add or subtract covers -n <= p < 2n; anything further out
+// (tiles wider than the mesh) takes the remainder.
 __device__ __forceinline__ int map_index(int p, int n, int bc) {
   if (bc == kOutflow) return p < 0 ? 0 : (p >= n ? n - 1 : p);
-  if (n >= 8) {
-    p += (p < 0) ? n : 0;
-    p -= (p >= n) ? n : 0;
-    return p;
+  p += (p < 0) ? n : 0;
+  p -= (p >= n) ? n : 0;
+  if ((unsigned)p >= (unsigned)n) {
+    const int r = p % n;
+    p = r < 0 ? r + n : r;
   }
-  int r = p % n;
-  return r < 0 ? r + n : r;
+  return p;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,5 +1,6 @@
 // Kernel instantiations for float, 2D.
 #include "euler_kernels.h"
+#include "euler_march2d.h"
 #include "kernel_table.h"
 
 namespace paraiso {
@@ -13,6 +14,10 @@ const KernelTable* table_f32_2() {
       PARAISO_SET(k_stage_lds),
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
+      {(const void*)k_march2d<float, 0, true>, (const void*)k_march2d<float, 3, true>,
+       (const void*)k_march2d<float, 4, true>, (const void*)k_march2d<float, 5, true>},
+      {(const void*)k_march2d<float, 0, false>, (const void*)k_march2d<float, 3, false>,
+       (const void*)k_march2d<float, 4, false>, (const void*)k_march2d<float, 5, false>},
       (const void*)k_cfl<float, 2>,
       (const void*)k_totals_partial<float, 2>,
       (const void*)k_totals_final<2>,

@@ -13,6 +13,8 @@ const KernelTable* table_f32_3() {
       PARAISO_SET(k_stage_lds),
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
+      {nullptr, nullptr, nullptr, nullptr},
+      {nullptr, nullptr, nullptr, nullptr},
       (const void*)k_cfl<float, 3>,
       (const void*)k_totals_partial<float, 3>,
       (const void*)k_totals_final<3>,

@@ -1,5 +1,6 @@
 // Kernel instantiations for double, 2D.
 #include "euler_kernels.h"
+#include "euler_march2d.h"
 #include "kernel_table.h"
 
 namespace paraiso {
@@ -13,6 +14,10 @@ const KernelTable* table_f64_2() {
       PARAISO_SET(k_stage_lds),
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
+      {(const void*)k_march2d<double, 0, true>, (const void*)k_march2d<double, 3, true>,
+       (const void*)k_march2d<double, 4, true>, (const void*)k_march2d<double, 5, true>},
+      {(const void*)k_march2d<double, 0, false>, (const void*)k_march2d<double, 3, false>,
+       (const void*)k_march2d<double, 4, false>, (const void*)k_march2d<double, 5, false>},
       (const void*)k_cfl<double, 2>,
       (const void*)k_totals_partial<double, 2>,
       (const void*)k_totals_final<2>,

@@ -11,6 +11,8 @@ struct KernelTable {
   const void* stage_lds[4];
   const void* fused_lds[4];
   const void* fused_direct[4];
+  const void* march_fused[4];  // 2D register march (null for other dimensions)
+  const void* march_stage[4];
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;

@@ -168,6 +168,7 @@ struct paraiso_ctx {
   int xcd_begin[9] = {};
   LdsGeom geom{};
   Launch step;  // fused kernel, or the stage kernel launched twice
+  int eff_tile[3] = {1, 1, 1};  // tile of one work item for the kernels
   int cur = 0, ring = 0;
   hipGraphExec_t graph[6] = {};
   int device = 0, num_cus = 0, max_lds = 0;
@@ -203,7 +204,7 @@ Args base_args(const paraiso_ctx* c) {
   a.partials = c->d_partials;
   a.nmeshes = c->count;
   a.nitems = c->nitems;
-  for (int k = 0; k < 3; ++k) a.tile[k] = c->var.tile[k];
+  for (int k = 0; k < 3; ++k) a.tile[k] = c->eff_tile[k];
   a.persistent = c->persistent ? 1 : 0;
   for (int k = 0; k < 9; ++k) a.xcd_begin[k] = c->xcd_begin[k];
   return a;
@@ -306,7 +307,16 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
       return PARAISO_ERR_UNSUPPORTED;
     }
   }
-  if (v.lds != 0 && v.lds != 1) return why = "lds must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
+  if (v.lds < 0 || v.lds > 2) return why = "lds must be 0, 1 or 2", PARAISO_ERR_UNSUPPORTED;
+  if (v.lds == 2) {
+    if (d != 2) return why = "register march (lds = 2) exists for 2D meshes only", PARAISO_ERR_UNSUPPORTED;
+    for (const auto& m : c->meshes)
+      if (m.bc[0] != PARAISO_PERIODIC || m.bc[1] != PARAISO_PERIODIC)
+        return why = "register march (lds = 2) needs periodic boundaries", PARAISO_ERR_UNSUPPORTED;
+    if (v.tile[0] != 64) return why = "register march: tile[0] must be 64 (one wave of columns)", PARAISO_ERR_UNSUPPORTED;
+    if (v.threads != 0 && (v.threads < 64 || v.threads > 256 || v.threads % 64))
+      return why = "register march: threads must be 64, 128, 192 or 256", PARAISO_ERR_UNSUPPORTED;
+  }
   if (v.fuse != 0 && v.fuse != 1) return why = "fuse must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
@@ -325,13 +335,20 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   if (rc) return fail(rc, "variant: " + why);
   const int d = c->ndim, nf = d + 2;
   const int threads = v.threads ? v.threads : 256;
+  // tile of one work item: the variant's tile, or for the register march
+  // (64 - 2H) columns by rows-per-wave times waves-per-block
+  int et[3] = {v.tile[0], v.tile[1], v.tile[2]};
+  if (v.lds == 2) {
+    et[0] = 64 - 2 * (v.fuse ? 4 : 2);
+    et[1] = v.tile[1] * (threads / 64);
+  }
   // items
   int64_t items = 0;
   for (int m = 0; m < c->count; ++m) {
     MeshDev& M = c->hm[m];
     int64_t nt = 1;
     for (int a = 0; a < 3; ++a) {
-      M.nt[a] = (int)((M.n[a] + v.tile[a] - 1) / v.tile[a]);
+      M.nt[a] = (int)((M.n[a] + et[a] - 1) / et[a]);
       nt *= M.nt[a];
     }
     if (items + nt >= (int64_t(1) << 31)) return fail(PARAISO_ERR_UNSUPPORTED, "variant: too many tiles");
@@ -369,7 +386,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   }
   G.vstride = G.vin.count;
   G.fstride = fmax_count;
-  if (v.lds) {
+  if (v.lds == 1) {
     shmem = (size_t)c->esize * nf * ((size_t)G.vstride + G.fstride);
     const size_t static_lds = 16 * sizeof(double) + 64;
     if (shmem + static_lds > (size_t)c->max_lds)
@@ -383,8 +400,10 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   // periodic wrap; nothing else to check
   const int ws = waves_slot(v.waves_per_eu);
   Launch L;
-  if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
+  if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
+  else if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
   else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
+  if (!L.fn) return fail(PARAISO_ERR_UNSUPPORTED, "variant: no kernel for this combination");
   L.block = dim3(threads);
   L.shmem = shmem;
   L.with_geom = true;
@@ -414,6 +433,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   drop_graphs(c);
   v.threads = threads;
   c->var = v;
+  for (int a = 0; a < 3; ++a) c->eff_tile[a] = et[a];
   c->fused = v.fuse != 0;
   c->lds = v.lds != 0;
   c->persistent = v.persistent != 0;

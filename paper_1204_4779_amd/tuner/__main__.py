@@ -58,11 +58,13 @@ def gain_study(db: DB, ndim: int, esize: int, seeds: int = 9, frac: float = 0.1,
                 seedv = [cands[int(i)] for i in rng.permutation(len(cands))[:8]]
                 tr = search.pagsa(cands, ev, budget, rng, ndim, seedv)
             res.append({"seed": s, "best_frac": tr.best_mu / truth.best_mu, "best_key": tr.best_key,
-                        "spent": tr.spent, "evaluated": len(tr.evaluated)})
-            log(f"{name} seed {s}: best {tr.best_mu / truth.best_mu:.4f} of optimum after "
-                f"{len(tr.evaluated)} benchmarks, {tr.spent:.1f} s")
+                        "anytime": tr.anytime(truth.best_mu, budget), "spent": tr.spent,
+                        "evaluated": len(tr.evaluated)})
+            log(f"{name} seed {s}: best {tr.best_mu / truth.best_mu:.4f} of optimum, anytime "
+                f"{res[-1]['anytime']:.4f}, after {len(tr.evaluated)} benchmarks, {tr.spent:.1f} s")
         out["runs"][name] = res
         out[f"{name}_median"] = float(np.median([r["best_frac"] for r in res]))
+        out[f"{name}_anytime_median"] = float(np.median([r["anytime"] for r in res]))
     return out
 
 

@@ -36,6 +36,18 @@ class Trace:
         if mu > self.best_mu:
             self.best_mu, self.best_key = mu, k
 
+    def anytime(self, optimum: float, budget: float) -> float:
+        """Mean over the budget of the best-so-far fraction of the optimum (area under the
+        best-so-far curve, benchmark seconds on the x axis, normalised to 1)."""
+        area, t, best = 0.0, 0.0, 0.0
+        for _, mu, cost in self.evaluated:
+            step = min(cost, max(budget - t, 0.0))
+            area += best * step
+            t += step
+            best = max(best, mu / optimum)
+        area += best * max(budget - t, 0.0)
+        return area / budget
+
 
 class ReplayEvaluator:
     """Answers from a database of measured individuals (exhaustive run)."""

@@ -1,9 +1,12 @@
 """Variant space, genome encoding and features.
 
-A variant is (tile per axis, LDS staging, RK-stage fusion, waves-per-EU hint).
-The genome is its bit string: 2 bits per active axis for the tile
-(8, 16, 32, 64), one bit each for LDS and fusion, 2 bits for the hint
-(0 = compiler's choice, 3, 4, 5).  The paper's genome encodes Manifest /
+A variant is (tile per axis, staging, RK-stage fusion, waves-per-EU hint).
+Staging: 0 = each cell reads its stencil from global memory, 1 = LDS tiles,
+2 = register march (2D only: a wave per 64-column strip marching along y,
+x-neighbours through DPP lane shifts; tile[0] is then 64 and tile[1] the
+rows per wave).  The genome is its bit string: 2 bits per active axis for
+the tile (8, 16, 32, 64), 2 bits for staging, 1 bit for fusion, 2 bits for
+the hint (0 = compiler's choice, 3, 4, 5).  The paper's genome encodes Manifest /
 Delayed choices and launch configurations of generated code ("Tuning
 Targets"); here LDS staging and stage fusion are the storage-versus-recompute
 choices and tile and occupancy hint are the launch configuration.
@@ -22,7 +25,7 @@ STATIC_LDS = 16 * 8 + 64
 
 def threads_for(variant: dict, ndim: int) -> int:
     """Workgroup size: 256, or 512 when an LDS tile needs more than KMAXR cells per thread."""
-    if not variant["lds"]:
+    if variant["lds"] != 1:
         return 256
     c1 = region(variant, ndim, 2 if variant["fuse"] else 0)
     tile = region(variant, ndim, 0)
@@ -59,6 +62,8 @@ def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
 
 
 def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
+    if variant["lds"] == 2:
+        return ndim == 2 and variant["tile"][0] == 64
     if not variant["lds"]:
         return True
     if lds_bytes(variant, ndim, esize) + STATIC_LDS > MAX_LDS_BYTES:
@@ -69,6 +74,8 @@ def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
 
 def make_variant(tile, lds, fuse, waves, ndim) -> dict:
     t = tuple(tile) + (1,) * (3 - len(tile))
+    if lds == 2:
+        t = (64,) + t[1:]
     v = {"tile": t, "lds": int(lds), "fuse": int(fuse), "waves_per_eu": int(waves)}
     v["threads"] = threads_for(v, ndim)
     return v
@@ -81,6 +88,11 @@ def enumerate_space(ndim: int) -> list:
             for fuse in (0, 1):
                 for w in WAVE_VALUES:
                     out.append(make_variant(tile, lds, fuse, w, ndim))
+    if ndim == 2:
+        for rows in TILE_VALUES:
+            for fuse in (0, 1):
+                for w in WAVE_VALUES:
+                    out.append(make_variant((64, rows), 2, fuse, w, ndim))
     return out
 
 
@@ -92,7 +104,7 @@ def key(variant: dict) -> str:
 # ---- genome -------------------------------------------------------------------------------
 
 def genome_bits(ndim: int) -> int:
-    return 2 * ndim + 4
+    return 2 * ndim + 5
 
 
 def encode(variant: dict, ndim: int) -> str:
@@ -100,7 +112,7 @@ def encode(variant: dict, ndim: int) -> str:
     for a in range(ndim):
         i = TILE_VALUES.index(variant["tile"][a])
         bits += [(i >> 1) & 1, i & 1]
-    bits += [variant["lds"], variant["fuse"]]
+    bits += [(variant["lds"] >> 1) & 1, variant["lds"] & 1, variant["fuse"]]
     w = WAVE_VALUES.index(variant["waves_per_eu"])
     bits += [(w >> 1) & 1, w & 1]
     return "".join(str(b) for b in bits)
@@ -112,7 +124,8 @@ def decode(genome: str, ndim: int) -> dict:
         raise ValueError("genome length")
     tile = [TILE_VALUES[b[2 * a] * 2 + b[2 * a + 1]] for a in range(ndim)]
     o = 2 * ndim
-    return make_variant(tile, b[o], b[o + 1], WAVE_VALUES[b[o + 2] * 2 + b[o + 3]], ndim)
+    lds = b[o] * 2 + b[o + 1]
+    return make_variant(tile, lds, b[o + 2], WAVE_VALUES[b[o + 3] * 2 + b[o + 4]], ndim)
 
 
 # ---- features of the cost model ---------------------------------------------------------
@@ -124,12 +137,13 @@ def features(variant: dict, ndim: int, esize: int) -> list:
     loads = region(variant, ndim, 4 if variant["fuse"] else 2) / cells
     w = variant["waves_per_eu"]
     f = [math.log2(t[a]) / 6.0 for a in range(3)]
-    f += [float(variant["lds"]), float(variant["fuse"]), float(variant["lds"] * variant["fuse"])]
+    f += [1.0 if variant["lds"] == k else 0.0 for k in (0, 1, 2)]
+    f += [float(variant["fuse"]), float((variant["lds"] > 0) * variant["fuse"])]
     f += [1.0 if w == x else 0.0 for x in WAVE_VALUES]
     f += [math.log2(cells) / 18.0, halo / 4.0, math.log2(loads) / 4.0,
-          lds_bytes(variant, ndim, esize) / MAX_LDS_BYTES if variant["lds"] else 0.0,
+          lds_bytes(variant, ndim, esize) / MAX_LDS_BYTES if variant["lds"] == 1 else 0.0,
           variant["threads"] / 512.0]
     return f
 
 
-N_FEATURES = 16
+N_FEATURES = 18

@@ -211,3 +211,43 @@ def test_set_variant_rejects_oversized_lds():
     assert ei.value.code == pb.ERR_UNSUPPORTED
     # the previous variant is still in place and works
     s.step(1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("fuse", [1, 0])
+@pytest.mark.parametrize("n", [(200, 77), (37, 21), (64, 64), (5, 9), (130, 3)])
+def test_register_march_matches_oracle(dtype, fuse, n):
+    pr = inputs.random_state(2, n, seed=300 + n[0], rough=True)
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.5)
+    ref = oracle.step(m, U0, dt)
+    for rows, threads in ((8, 256), (16, 64), (64, 128)):
+        v = dict(tile=(64, rows), lds=2, fuse=fuse, threads=threads)
+        s = gpu_solver(spec_of(pr), dtype, v, pr.U)
+        s.step(dt)
+        err = rel_err(gpu_state(s), ref)
+        assert err <= TOL[dtype], (v, err)
+
+
+def test_register_march_advance_and_batch():
+    probs = [inputs.blob_2d(n, 12044779, k) for k, n in enumerate((40, 72, 33, 130))]
+    specs = [spec_of(p) for p in probs]
+    v = dict(tile=(64, 16), lds=2, fuse=1, persistent=1)
+    b = gpu_solver(specs, "f64", v, [p.U for p in probs])
+    t, n = b.advance(0.01, 0.5, t0=[0.0] * 4)
+    for k, p in enumerate(probs):
+        ref, t_ref, n_ref = oracle.advance(oracle_mesh(p), p.U, 0.5, 0.01)
+        assert n[k] == n_ref and t[k] == t_ref
+        assert rel_err(gpu_state(b, k), ref) < 1e-11
+
+
+def test_register_march_rejects_outflow_and_3d():
+    pr = inputs.random_state(2, (40, 30), seed=1, bc=(1, 0))
+    s = gpu_solver(spec_of(pr), "f32", None, pr.U)
+    with pytest.raises(pb.ParaisoError):
+        s.set_variant(dict(tile=(64, 16), lds=2, fuse=1))
+    pr3 = inputs.random_state(3, (8, 8, 8), seed=1)
+    s3 = gpu_solver(spec_of(pr3), "f32", None, pr3.U)
+    with pytest.raises(pb.ParaisoError):
+        s3.set_variant(dict(tile=(64, 16, 1), lds=2, fuse=1))
