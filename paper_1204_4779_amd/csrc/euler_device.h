@@ -84,10 +84,10 @@ struct Fp<float> {
   static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
   static __device__ __forceinline__ float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
   static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
-  // true when a and b carry the same sign bit
-  static __device__ __forceinline__ bool same_sign(float a, float b) {
-    return (__float_as_int(a) ^ __float_as_int(b)) >= 0;
-  }
+  // sqrt(a / b) for a, b > 0 with a single transcendental: a * rsqrt(a b)
+  static __device__ __forceinline__ float sqrt_ratio(float a, float b) { return a * __builtin_amdgcn_rsqf(a * b); }
+  // median of (a, b, 0): zero unless a and b share a sign, else the smaller magnitude
+  static __device__ __forceinline__ float med0(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
 };
 
 template <>
@@ -95,8 +95,9 @@ struct Fp<double> {
   static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
   static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
   static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-  static __device__ __forceinline__ bool same_sign(double a, double b) {
-    return (__double2hiint(a) ^ __double2hiint(b)) >= 0;
+  static __device__ __forceinline__ double sqrt_ratio(double a, double b) { return ::sqrt(a / b); }
+  static __device__ __forceinline__ double med0(double a, double b) {
+    return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
   }
 };
 
@@ -110,12 +111,12 @@ struct Gas {
 
 // Limited slope of the Interpolate equation: 0 when the one-sided
 // differences differ in sign (or one is zero), otherwise the one of smaller
-// magnitude.  copysign(min(|a|,|b|), a) equals that choice bit for bit, ties
-// included, and needs no product (so no underflow to a false zero).
+// magnitude.  That is exactly the median of (a, b, 0), one v_med3_f32 in FP32:
+// no product is formed, so FP32 underflow cannot zero a valid slope, and a
+// tie returns a value equal to either difference.
 template <typename T>
 __device__ __forceinline__ T minmod(T a, T b) {
-  T m = fmin(fabs(a), fabs(b));
-  return Fp<T>::same_sign(a, b) ? copysign(m, a) : T(0);
+  return Fp<T>::med0(a, b);
 }
 
 // V(U): rho, v_a = m_a / rho, p = (gamma-1)(E - rho v^2/2).
@@ -154,23 +155,27 @@ __device__ __forceinline__ void face_states(T y0, T y1, T y2, T y3, T& left, T& 
 //   U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S*, v_t, E_K/rho_K
 //          + (S* - u_K)(S* + p_K / (rho_K (S_K - u_K)))).
 // The side is selected first so that one physical flux and one star state
-// are evaluated; E*_K is formed with the single reciprocal 1/(S_K - S*).
+// are evaluated; E*_K is formed as
+//   [(S_K - u_K) E_K + (S* - u_K)(rho_K (S_K - u_K) S* + p_K)] / (S_K - S*).
 template <typename T, int D, int AX>
 __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T>& g) {
   const T rl = vl[0], rr = vr[0];
   const T ul = vl[1 + AX], ur = vr[1 + AX];
   const T pl = vl[D + 1], pr = vr[D + 1];
-  const T cl = Fp<T>::sqrt(g.gamma * pl * Fp<T>::rcp(rl));
-  const T cr = Fp<T>::sqrt(g.gamma * pr * Fp<T>::rcp(rr));
+  const T cl = Fp<T>::sqrt_ratio(g.gamma * pl, rl);
+  const T cr = Fp<T>::sqrt_ratio(g.gamma * pr, rr);
   const T sl = fmin(ul - cl, ur - cr);
   const T sr = fmax(ul + cl, ur + cr);
   const T al = rl * (sl - ul);
   const T ar = rr * (sr - ur);
-  const T sstar = Fp<T>::div(pr - pl + al * ul - ar * ur, al - ar);
+  // S* = num / den with den = al - ar < 0 for positive densities and sound
+  // speeds, so 0 <= S* exactly when num <= 0
+  const T num = pr - pl + al * ul - ar * ur;
+  const T den = al - ar;
 
   const bool left_sup = (T(0) <= sl);
   const bool right_sup = (sr <= T(0));
-  const bool use_l = left_sup || (!right_sup && (T(0) <= sstar));
+  const bool use_l = left_sup || (!right_sup && (num <= T(0)));
 
   T vk[D + 2];
 #pragma unroll
@@ -184,10 +189,14 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
   for (int b = 0; b < D; ++b) v2 += vk[1 + b] * vk[1 + b];
   const T ek = pk * g.inv_gm1 + T(0.5) * rk * v2;
 
+  // one reciprocal gives both S* = num/den and 1/(S_K - S*) = den/(S_K den - num)
+  const T e = sk * den - num;
+  const T r = Fp<T>::rcp(den * e);
   // weight of the star correction: zero on supersonic faces
   const bool sup = left_sup || right_sup;
   const T w = sup ? T(0) : sk;
-  const T inv = sup ? T(0) : Fp<T>::rcp(sk - sstar);
+  const T sstar = sup ? T(0) : num * e * r;
+  const T inv = sup ? T(0) : den * den * r;
   const T rstar = ak * inv;
   const T estar = inv * ((sk - uk) * ek + (sstar - uk) * (ak * sstar + pk));
 

@@ -220,14 +220,16 @@ struct LdsGeom {
 
 template <typename T, int D>
 struct Fields {
-  T* f[D + 2];
+  // field arrays live in device global memory: typing them so lets the
+  // compiler emit global (not flat) loads and stores
+  __attribute__((address_space(1))) T* f[D + 2];
 };
 
 template <typename T, int D>
 __device__ __forceinline__ Fields<T, D> fields(void* const* p) {
   Fields<T, D> r;
 #pragma unroll
-  for (int q = 0; q < D + 2; ++q) r.f[q] = reinterpret_cast<T*>(p[q]);
+  for (int q = 0; q < D + 2; ++q) r.f[q] = (__attribute__((address_space(1))) T*)(p[q]);
   return r;
 }
 
