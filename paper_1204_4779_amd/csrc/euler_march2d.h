@@ -109,7 +109,8 @@ __device__ __forceinline__ bool pipe_push(RowPipe<T>& P, const T* c, int n, cons
   return done;
 }
 
-// Fused step (FUSED) or one stage (!FUSED) of a 2D periodic mesh.
+// Fused step (FUSED, periodic meshes) or one stage (!FUSED, periodic or
+// outflow: the stage's ghost cells are clamped loads of its input).
 // Block = threads/64 waves; the block tile is (64 - 2H) columns by
 // (waves * rows) rows, wave w taking rows [w*rows, (w+1)*rows) of it.
 template <typename T, int W, bool FUSED>
@@ -132,7 +133,7 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
     const int nx = M.n[0], ny = M.n[1];
     const int x0 = t.org[0], y0 = t.org[1] + wave * rows;
     const int y1 = min(y0 + rows, ny);
-    const int col = map_index(x0 - H + lane, nx, kPeriodic);
+    const int col = map_index(x0 - H + lane, nx, FUSED ? kPeriodic : M.bc[0]);
     const bool store_lane = lane >= H && lane < 64 - H && (x0 - H + lane) < nx;
     const Fields<T, 2> U0 = fields<T, 2>(M.s[a.src]);
     const Fields<T, 2> Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
@@ -160,7 +161,7 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
         int n1 = 0, n2 = 0;
         T nxt[4];
         {
-          const int gi = map_index(first, ny, kPeriodic) * nx + col;
+          const int gi = map_index(first, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
 #pragma unroll
           for (int q = 0; q < 4; ++q) nxt[q] = Uin.f[q][gi];
         }
@@ -169,7 +170,7 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
 #pragma unroll
           for (int q = 0; q < 4; ++q) u[q] = nxt[q];
           if (k + 1 < npush) {
-            const int gi = map_index(first + k + 1, ny, kPeriodic) * nx + col;
+            const int gi = map_index(first + k + 1, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
 #pragma unroll
             for (int q = 0; q < 4; ++q) nxt[q] = Uin.f[q][gi];
           }
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
 #pragma unroll
             for (int q = 0; q < 4; ++q) base[q] = u[q];
           } else {
-            const int gi = map_index(first + k, ny, kPeriodic) * nx + col;
+            const int gi = map_index(first + k, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
 #pragma unroll
             for (int q = 0; q < 4; ++q) base[q] = U0.f[q][gi];
           }

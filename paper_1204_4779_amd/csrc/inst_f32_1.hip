@@ -15,6 +15,7 @@ const KernelTable* table_f32_1() {
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      {nullptr, nullptr, nullptr, nullptr},
       (const void*)k_cfl<float, 1>,
       (const void*)k_totals_partial<float, 1>,
       (const void*)k_totals_final<1>,

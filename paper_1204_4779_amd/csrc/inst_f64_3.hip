@@ -1,5 +1,6 @@
 // Kernel instantiations for double, 3D.
 #include "euler_kernels.h"
+#include "euler_march3d.h"
 #include "kernel_table.h"
 
 namespace paraiso {
@@ -15,6 +16,8 @@ const KernelTable* table_f64_3() {
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      {(const void*)k_march3d<double, 0>, (const void*)k_march3d<double, 3>, (const void*)k_march3d<double, 4>,
+       (const void*)k_march3d<double, 5>},
       (const void*)k_cfl<double, 3>,
       (const void*)k_totals_partial<double, 3>,
       (const void*)k_totals_final<3>,

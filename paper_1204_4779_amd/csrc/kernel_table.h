@@ -13,6 +13,7 @@ struct KernelTable {
   const void* fused_direct[4];
   const void* march_fused[4];  // 2D register march (null for other dimensions)
   const void* march_stage[4];
+  const void* march3d_stage[4];  // 3D register march, one stage (null for other dimensions)
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;

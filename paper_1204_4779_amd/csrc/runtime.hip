@@ -309,15 +309,23 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   }
   if (v.lds < 0 || v.lds > 2) return why = "lds must be 0, 1 or 2", PARAISO_ERR_UNSUPPORTED;
   if (v.lds == 2) {
-    if (d != 2) return why = "register march (lds = 2) exists for 2D meshes only", PARAISO_ERR_UNSUPPORTED;
-    for (const auto& m : c->meshes)
-      if (m.bc[0] != PARAISO_PERIODIC || m.bc[1] != PARAISO_PERIODIC)
-        return why = "register march (lds = 2) needs periodic boundaries", PARAISO_ERR_UNSUPPORTED;
+    if (d == 1) return why = "register march (lds = 2) exists for 2D and 3D meshes", PARAISO_ERR_UNSUPPORTED;
     if (v.tile[0] != 64) return why = "register march: tile[0] must be 64 (one wave of columns)", PARAISO_ERR_UNSUPPORTED;
-    if (v.threads != 0 && (v.threads < 64 || v.threads > 256 || v.threads % 64))
-      return why = "register march: threads must be 64, 128, 192 or 256", PARAISO_ERR_UNSUPPORTED;
+    if (d == 2) {
+      if (v.fuse)
+        for (const auto& m : c->meshes)
+          if (m.bc[0] != PARAISO_PERIODIC || m.bc[1] != PARAISO_PERIODIC)
+            return why = "fused register march needs periodic boundaries", PARAISO_ERR_UNSUPPORTED;
+      if (v.threads != 0 && (v.threads < 64 || v.threads > 256 || v.threads % 64))
+        return why = "register march: threads must be 64, 128, 192 or 256", PARAISO_ERR_UNSUPPORTED;
+    } else {
+      if (v.fuse) return why = "3D register march is a one-stage kernel (fuse = 0)", PARAISO_ERR_UNSUPPORTED;
+      if (v.tile[1] != 4 && v.tile[1] != 8)
+        return why = "3D register march: tile[1] (rows = waves per block) must be 4 or 8", PARAISO_ERR_UNSUPPORTED;
+      if (v.threads != 0 && v.threads != 64 * v.tile[1])
+        return why = "3D register march: threads must be 64 * tile[1]", PARAISO_ERR_UNSUPPORTED;
+    }
   }
-  if (v.fuse != 0 && v.fuse != 1) return why = "fuse must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
@@ -334,13 +342,15 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   int rc = validate_variant(c, v, why);
   if (rc) return fail(rc, "variant: " + why);
   const int d = c->ndim, nf = d + 2;
-  const int threads = v.threads ? v.threads : 256;
+  const int threads = (v.lds == 2 && d == 3) ? 64 * v.tile[1] : (v.threads ? v.threads : 256);
   // tile of one work item: the variant's tile, or for the register march
   // (64 - 2H) columns by rows-per-wave times waves-per-block
   int et[3] = {v.tile[0], v.tile[1], v.tile[2]};
-  if (v.lds == 2) {
+  if (v.lds == 2 && d == 2) {
     et[0] = 64 - 2 * (v.fuse ? 4 : 2);
     et[1] = v.tile[1] * (threads / 64);
+  } else if (v.lds == 2) {
+    et[0] = 60;  // rows = waves, planes = tile[2]
   }
   // items
   int64_t items = 0;
@@ -386,6 +396,12 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   }
   G.vstride = G.vin.count;
   G.fstride = fmax_count;
+  if (v.lds == 2 && d == 3) {
+    const int nw = v.tile[1];
+    shmem = (size_t)c->esize * 5 * 64 * (2 * (size_t)(nw + 4) + 3 * (size_t)(nw + 1));
+    if (shmem + 16 * sizeof(double) + 64 > (size_t)c->max_lds)
+      return fail(PARAISO_ERR_UNSUPPORTED, "variant: 3D march needs " + std::to_string(shmem) + " bytes of LDS");
+  }
   if (v.lds == 1) {
     shmem = (size_t)c->esize * nf * ((size_t)G.vstride + G.fstride);
     const size_t static_lds = 16 * sizeof(double) + 64;
@@ -400,7 +416,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   // periodic wrap; nothing else to check
   const int ws = waves_slot(v.waves_per_eu);
   Launch L;
-  if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
+  if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
+  else if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
   else if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
   else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
   if (!L.fn) return fail(PARAISO_ERR_UNSUPPORTED, "variant: no kernel for this combination");

@@ -17,6 +17,7 @@ import itertools
 import math
 
 TILE_VALUES = (8, 16, 32, 64)
+MARCH3D_ROWS = (4, 8, 16, 32)   # rows (= waves) per block of the 3D register march; 16, 32 invalid
 WAVE_VALUES = (0, 3, 4, 5)
 KMAXR = 8                  # cells per thread the LDS kernels keep in registers
 MAX_LDS_BYTES = 160 * 1024  # per workgroup on gfx950
@@ -24,7 +25,10 @@ STATIC_LDS = 16 * 8 + 64
 
 
 def threads_for(variant: dict, ndim: int) -> int:
-    """Workgroup size: 256, or 512 when an LDS tile needs more than KMAXR cells per thread."""
+    """Workgroup size: 256, or 512 when an LDS tile needs more than KMAXR cells per thread;
+    the 3D register march runs one wave per tile row."""
+    if variant["lds"] == 2 and ndim == 3:
+        return 64 * variant["tile"][1]
     if variant["lds"] != 1:
         return 256
     c1 = region(variant, ndim, 2 if variant["fuse"] else 0)
@@ -63,7 +67,10 @@ def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
 
 def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
     if variant["lds"] == 2:
-        return ndim == 2 and variant["tile"][0] == 64
+        if ndim == 2:
+            return variant["tile"][0] == 64
+        return (ndim == 3 and variant["tile"][0] == 64 and variant["tile"][1] in (4, 8)
+                and not variant["fuse"])
     if not variant["lds"]:
         return True
     if lds_bytes(variant, ndim, esize) + STATIC_LDS > MAX_LDS_BYTES:
@@ -93,6 +100,12 @@ def enumerate_space(ndim: int) -> list:
             for fuse in (0, 1):
                 for w in WAVE_VALUES:
                     out.append(make_variant((64, rows), 2, fuse, w, ndim))
+    if ndim == 3:
+        for rows in MARCH3D_ROWS:
+            for planes in TILE_VALUES:
+                for fuse in (0, 1):
+                    for w in WAVE_VALUES:
+                        out.append(make_variant((64, rows, planes), 2, fuse, w, ndim))
     return out
 
 
@@ -107,10 +120,14 @@ def genome_bits(ndim: int) -> int:
     return 2 * ndim + 5
 
 
+def _axis_values(lds: int, ndim: int, a: int):
+    return MARCH3D_ROWS if (lds == 2 and ndim == 3 and a == 1) else TILE_VALUES
+
+
 def encode(variant: dict, ndim: int) -> str:
     bits = []
     for a in range(ndim):
-        i = TILE_VALUES.index(variant["tile"][a])
+        i = _axis_values(variant["lds"], ndim, a).index(variant["tile"][a])
         bits += [(i >> 1) & 1, i & 1]
     bits += [(variant["lds"] >> 1) & 1, variant["lds"] & 1, variant["fuse"]]
     w = WAVE_VALUES.index(variant["waves_per_eu"])
@@ -122,9 +139,9 @@ def decode(genome: str, ndim: int) -> dict:
     b = [int(c) for c in genome]
     if len(b) != genome_bits(ndim):
         raise ValueError("genome length")
-    tile = [TILE_VALUES[b[2 * a] * 2 + b[2 * a + 1]] for a in range(ndim)]
     o = 2 * ndim
     lds = b[o] * 2 + b[o + 1]
+    tile = [_axis_values(lds, ndim, a)[b[2 * a] * 2 + b[2 * a + 1]] for a in range(ndim)]
     return make_variant(tile, lds, b[o + 2], WAVE_VALUES[b[o + 3] * 2 + b[o + 4]], ndim)
 
 

@@ -13,9 +13,9 @@ TUNED = {
     # register march, fused RK, 16 rows per wave, 4 waves per block
     ("kh2048", "f32"): dict(tile=(64, 16), lds=2, fuse=1, waves_per_eu=0, threads=256),
     ("kh2048", "f64"): dict(tile=(64, 16), lds=2, fuse=1, waves_per_eu=0, threads=256),
-    # exhaustive optimum of the 512^3 box (tuner database): per-cell stencil, unfused, VGPR cap 168
-    ("box256", "f32"): dict(tile=(16, 16, 32), lds=0, fuse=0, waves_per_eu=3, threads=256),
-    ("box512", "f32"): dict(tile=(16, 16, 32), lds=0, fuse=0, waves_per_eu=3, threads=256),
+    # 3D register march, one stage per launch: 60 columns x 4 rows per block, 64-plane chunks
+    ("box256", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=0),
+    ("box512", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=0),
     ("batch512", "f32"): dict(tile=(64, 16), lds=2, fuse=1, waves_per_eu=0, threads=256, persistent=1),
     ("sod1024", "f64"): dict(tile=(256,), lds=1, fuse=1, waves_per_eu=0, threads=256),
 }

@@ -242,12 +242,79 @@ def test_register_march_advance_and_batch():
         assert rel_err(gpu_state(b, k), ref) < 1e-11
 
 
-def test_register_march_rejects_outflow_and_3d():
+def test_register_march_rejects_unsupported():
     pr = inputs.random_state(2, (40, 30), seed=1, bc=(1, 0))
     s = gpu_solver(spec_of(pr), "f32", None, pr.U)
     with pytest.raises(pb.ParaisoError):
-        s.set_variant(dict(tile=(64, 16), lds=2, fuse=1))
+        s.set_variant(dict(tile=(64, 16), lds=2, fuse=1))      # fused march needs periodic
     pr3 = inputs.random_state(3, (8, 8, 8), seed=1)
     s3 = gpu_solver(spec_of(pr3), "f32", None, pr3.U)
     with pytest.raises(pb.ParaisoError):
-        s3.set_variant(dict(tile=(64, 16, 1), lds=2, fuse=1))
+        s3.set_variant(dict(tile=(64, 8, 16), lds=2, fuse=1))  # 3D march is one stage
+    with pytest.raises(pb.ParaisoError):
+        s3.set_variant(dict(tile=(64, 2, 16), lds=2, fuse=0))  # 4 or 8 rows per block
+    pr1 = inputs.random_state(1, (100,), seed=1)
+    s1 = gpu_solver(spec_of(pr1), "f32", None, pr1.U)
+    with pytest.raises(pb.ParaisoError):
+        s1.set_variant(dict(tile=(64,), lds=2, fuse=0))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("n", [(19, 11, 10), (70, 9, 7), (130, 20, 5), (5, 4, 3)])
+def test_register_march_3d_matches_oracle(dtype, bc, n):
+    pr = inputs.random_state(3, n, seed=400 + n[0] + bc, rough=True, bc=(bc,) * 3)
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.5)
+    ref = oracle.step(m, U0, dt)
+    for rows, planes in ((4, 8), (8, 32), (4, 64)):
+        v = dict(tile=(64, rows, planes), lds=2, fuse=0)
+        s = gpu_solver(spec_of(pr), dtype, v, pr.U)
+        s.step(dt)
+        err = rel_err(gpu_state(s), ref)
+        assert err <= TOL[dtype], (v, err)
+
+
+def test_register_march_2d_unfused_outflow():
+    pr = inputs.random_state(2, (90, 41), seed=8, rough=True, bc=(1, 1))
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, pr.U, 0.5)
+    ref = oracle.step(m, pr.U, dt)
+    s = gpu_solver(spec_of(pr), "f64", dict(tile=(64, 16), lds=2, fuse=0), pr.U)
+    s.step(dt)
+    assert rel_err(gpu_state(s), ref) <= 1e-12
+
+
+def test_register_march_3d_advance_matches_oracle():
+    pr = inputs.random_state(3, (40, 24, 20), seed=77)
+    ref, t_ref, n_ref = oracle.advance(oracle_mesh(pr), pr.U, 0.5, 1e9, max_steps=8)
+    s = gpu_solver(spec_of(pr), "f64", dict(tile=(64, 8, 16), lds=2, fuse=0), pr.U)
+    t, n = s.advance(1e9, 0.5, max_steps=8)
+    assert n == [8] and abs(t[0] - t_ref) <= 1e-13 * t_ref
+    assert rel_err(gpu_state(s), ref) < 1e-11
+
+
+@pytest.mark.parametrize("vname", ["march2d", "lds_fused", "lds"])
+def test_graph_replays_interleaved_with_eager_work(vname):
+    # Each advance(6) replays one captured six-step graph; between replays run eager
+    # explicit steps, reductions and host reads.  Every replay must equal the same
+    # steps launched eagerly (advance with 5 + 1 steps never forms a graph).
+    pr = inputs.random_state(2, (128, 70), seed=91)
+    v = {"march2d": dict(tile=(64, 16), lds=2, fuse=1), "lds_fused": dict(tile=(32, 16), lds=1, fuse=1),
+         "lds": dict(tile=(32, 16), lds=1, fuse=0)}[vname]
+    g = gpu_solver(spec_of(pr), "f64", v, pr.U)
+    e = gpu_solver(spec_of(pr), "f64", v, pr.U)
+    tg, te = [0.0], [0.0]
+    for rep in range(4):
+        tg, ng = g.advance(float("inf"), 0.5, max_steps=6, t0=tg)
+        for k in (5, 1):
+            te, _ = e.advance(float("inf"), 0.5, max_steps=k, t0=te)
+        assert ng == [6] and tg == te, rep
+        np.testing.assert_array_equal(gpu_state(g), gpu_state(e))
+        # eager work between replays on both contexts
+        dt = g.cfl_dt(0.4)[0]
+        assert dt == e.cfl_dt(0.4)[0]
+        g.step(dt)
+        e.step(dt)
+        assert g.totals() == e.totals()

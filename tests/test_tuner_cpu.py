@@ -19,7 +19,7 @@ def test_genome_round_trip(ndim):
         assert len(g) == sp.genome_bits(ndim)
         assert sp.decode(g, ndim) == v
         seen.add(g)
-    assert len(seen) == 4 ** ndim * 16 + (32 if ndim == 2 else 0)
+    assert len(seen) == 4 ** ndim * 16 + {1: 0, 2: 32, 3: 128}[ndim]
 
 
 def test_triangulation_table():
