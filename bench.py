@@ -137,6 +137,17 @@ def cpu_baseline(U, budget_s: float = 12.0):
             "sample": f"{steps} FP64 steps (+CFL) of the full 2048x2048 KH mesh, serial C, {el:.1f} s"}
 
 
+def calibration_copy():
+    """Three plain device copies of 512 MiB: known bytes that scale the HBM counters."""
+    import torch
+    src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("calibration copy: 536870912 bytes read and written per launch, 3 launches")
+
+
 def other_workload(name: str, steps: int, warmup: int):
     """Cell-updates/s of the other configurations (one JSON line each, not the headline)."""
     from paper_1204_4779_amd import binding as pb
@@ -211,6 +222,8 @@ def main():
     if args.workload != "kh2048":
         out = other_workload(args.workload, args.steps, args.warmup)
         out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "data": "synthetic"})
+        if args.prof:
+            calibration_copy()
         print(json.dumps(out))
         return
     log("generating KH 2048^2 input")
@@ -261,13 +274,7 @@ def main():
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_launch}
 
     if args.prof:
-        # plain copy of known size: 512 MiB read + 512 MiB written
-        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("calibration copy: 536870912 bytes read and written per launch, 3 launches")
+        calibration_copy()
 
     cpu = None
     if not args.no_cpu:

@@ -83,9 +83,20 @@ typedef struct paraiso_mesh {
  * Kernel variant (the tuning space).  These choices change speed, never
  * results beyond floating-point rounding.
  *   tile[a]      cells per workgroup tile along axis a (1 for unused axes);
- *   lds          1: stage primitive states and face fluxes through LDS, each
- *                face flux computed once per tile; 0: every cell computes
- *                its own 2d face fluxes from global memory;
+ *   lds          staging of the stencil:
+ *                0: every cell computes its own 2d face fluxes from global
+ *                   memory;
+ *                1: LDS tiles, each face flux computed once per tile;
+ *                2: register march (2D and 3D): a wave per strip of 64
+ *                   columns (tile[0] = 64) marching along the last axis,
+ *                   x-neighbours by lane shifts; 2D: tile[1] rows per wave;
+ *                   3D: tile[1] = 4 or 8 rows (= waves) per block, tile[2]
+ *                   planes per block, one stage per launch (fuse = 0); the
+ *                   fused 2D form needs periodic boundaries;
+ *                3: resident (1D, at most 4096 cells per mesh in FP32 and
+ *                   3407 in FP64, the LDS of one workgroup holding
+ *                   8 * (6n + 3) bytes): one workgroup per mesh runs a
+ *                   whole paraiso_advance in one launch;
  *   fuse         1: both Runge-Kutta stages in one launch, stage 1
  *                recomputed on a halo of 2 cells; 0: one launch per stage,
  *                stage-1 state kept in the workspace;

@@ -135,26 +135,46 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
       RowPipe5<T> P;
       const int first = z0 - 2;
       const int npush = (z1 - z0) + 4;
-      for (int k = 0; k < npush; ++k) {
-        const int zk = map_index(first + k, nz, M.bc[2]);
-        // own row
-        T u[5], v[5];
-        {
-          const int gi = zk * plane + yown * nx + col;
+      const int own_off = yown * nx + col, halo_off = yhalo * nx + col;
+      // loads run one plane ahead of their use (own row, halo row, base state)
+      T u_nx[5], uh_nx[5], base_nx[5];
 #pragma unroll
-          for (int q = 0; q < 5; ++q) u[q] = Uin.f[q][gi];
-        }
-        prim_of_cons<T, 3>(u, v, g);
+      for (int q = 0; q < 5; ++q) uh_nx[q] = base_nx[q] = T(0);
+      {
+        const int zk = map_index(first, nz, M.bc[2]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) u_nx[q] = Uin.f[q][zk * plane + own_off];
+      }
+      for (int k = 0; k < npush; ++k) {
         // only planes that are assembled need their y-faces (not the 2 + 2 halo planes)
         const bool yplane = k >= 2 && k < npush - 2;
+        T u[5], uh[5], base[5], v[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          u[q] = u_nx[q];
+          uh[q] = uh_nx[q];
+          base[q] = base_nx[q];
+        }
+        if (k + 1 < npush) {
+          const int zn = map_index(first + k + 1, nz, M.bc[2]);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) u_nx[q] = Uin.f[q][zn * plane + own_off];
+          if (has_halo && k + 1 >= 2 && k + 1 < npush - 2) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) uh_nx[q] = Uin.f[q][zn * plane + halo_off];
+          }
+          if (k + 1 >= 4) {  // base of the plane assembled at push k + 1
+            const int zb = first + k + 1 - 2;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) base_nx[q] = U0.f[q][zb * plane + own_off];
+          }
+        }
+        prim_of_cons<T, 3>(u, v, g);
         T* Vs = sV + (k & 1) * vslot;
 #pragma unroll
         for (int q = 0; q < 5; ++q) Vs[(q * NR + wave + 2) * 64 + lane] = v[q];
         if (has_halo && yplane) {
-          T uh[5], vh[5];
-          const int gi = zk * plane + yhalo * nx + col;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) uh[q] = Uin.f[q][gi];
+          T vh[5];
           prim_of_cons<T, 3>(uh, vh, g);
 #pragma unroll
           for (int q = 0; q < 5; ++q) Vs[(q * NR + hrel) * 64 + lane] = vh[q];
@@ -192,14 +212,14 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
           xflux_diff3<T>(va, g, dF);
           const T* Gs = sG + ((k + 1) % 3) * gslot;  // slot of plane k - 2
           T out[5];
-          const int gi = zo * plane + yown * nx + col;
+          const int gi = zo * plane + own_off;
 #pragma unroll
           for (int q = 0; q < 5; ++q) {
             const T dy = Gs[(q * (NW + 1) + wave) * 64 + lane] - Gs[(q * (NW + 1) + wave + 1) * 64 + lane];
             T acc = kx * dF[q];
             acc += ky * dy;
             acc += kz * accz[q];
-            out[q] = U0.f[q][gi] + acc;
+            out[q] = base[q] + acc;
           }
           if (store_lane) {
 #pragma unroll

@@ -1,0 +1,161 @@
+// Resident kernel for small 1D meshes (gfx950).
+//
+// One workgroup holds one whole mesh (up to kResidentCells cells, a few per
+// thread in registers, primitives and face fluxes exchanged through LDS) and
+// runs a whole advance in a single launch: each step forms the face fluxes
+// of stage 1 and stage 2 (one flux per face), the CFL maximum of the new
+// state as a block reduction in FP64, dt = cfl / max clamped to t_end, and
+// t and the step count, until t_end or the step budget is reached.  A 1D
+// shock tube of 1024 cells needs ~900 dependent steps; this removes the
+// per-step launch and scheduling latency that otherwise dominates.
+//
+// Modes: explicit dt (one step with a.dt[m]) or device-dt advance.  The
+// final state is written to buffer 1 - src, so the host counts one launch
+// as one buffer flip; t and the step count go to ring slot (ring + 1) % 3.
+#pragma once
+
+#include "euler_kernels.h"
+
+namespace paraiso {
+
+constexpr int kResidentThreads = 1024;
+constexpr int kResidentPerThread = 4;
+constexpr int kResidentCells = kResidentThreads * kResidentPerThread;
+
+template <typename T>
+__device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g, int n, T coef,
+                                               const T (*uin)[3], const T (*ubase)[3], T (*uout)[3], T* sV,
+                                               T* sF) {
+  const int tid = threadIdx.x;
+  // primitives of this thread's cells into LDS
+#pragma unroll
+  for (int r = 0; r < kResidentPerThread; ++r) {
+    const int i = tid + r * kResidentThreads;
+    if (i < n) {
+      T v[3];
+      prim_of_cons<T, 1>(uin[r], v, g);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sV[q * n + i] = v[q];
+    }
+  }
+  __syncthreads();
+  // face f lies between cells f-1 and f (f = 0..n)
+  for (int f = tid; f <= n; f += kResidentThreads) {
+    const int i0 = map_index(f - 2, n, M.bc[0]), i1 = map_index(f - 1, n, M.bc[0]);
+    const int i2 = map_index(f, n, M.bc[0]), i3 = map_index(f + 1, n, M.bc[0]);
+    T vl[3], vr[3], fl[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T* y = sV + q * n;
+      face_states(y[i0], y[i1], y[i2], y[i3], vl[q], vr[q]);
+    }
+    hllc<T, 1, 0>(vl, vr, fl, g);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sF[q * (n + 1) + f] = fl[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kResidentPerThread; ++r) {
+    const int i = tid + r * kResidentThreads;
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const T* F = sF + q * (n + 1);
+        uout[r][q] = ubase[r][q] + coef * (F[i] - F[i + 1]);
+      }
+    }
+  }
+  __syncthreads();  // sV / sF are rewritten by the next stage
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[16];
+  __shared__ int s_bad;
+  const int m = blockIdx.x;
+  const MeshDev& M = a.meshes[m];
+  const int n = M.n[0];
+  T* sV = reinterpret_cast<T*>(smem);  // [3][n]
+  T* sF = sV + 3 * n;                   // [3][n + 1]
+  const int tid = threadIdx.x;
+  const Gas<T> g = gas_of<T>(M);
+  const Fields<T, 1> U0 = fields<T, 1>(M.s[a.src]);
+  const Fields<T, 1> Uout = fields<T, 1>(M.s[1 - a.src]);
+  T u[kResidentPerThread][3], u1[kResidentPerThread][3];
+#pragma unroll
+  for (int r = 0; r < kResidentPerThread; ++r) {
+    const int i = tid + r * kResidentThreads;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) u[r][q] = i < n ? U0.f[q][i] : T(1);
+  }
+  const bool explicit_dt = a.dt != nullptr;
+  Ctl& c = a.ctl[m];
+  double t = explicit_dt ? 0.0 : c.t[a.ring];
+  long long steps = explicit_dt ? 0 : c.steps[a.ring];
+  double qmax = explicit_dt ? 0.0 : __longlong_as_double((long long)c.qbits[a.ring]);
+  const double t_end = explicit_dt ? 0.0 : a.prm->t_end;
+  const long long max_steps = explicit_dt ? 1 : a.prm->max_steps;
+  const double cfl = explicit_dt ? 0.0 : a.prm->cfl;
+  bool bad = false;
+  for (;;) {
+    double dt;
+    if (explicit_dt) {
+      if (steps >= 1) break;
+      dt = a.dt[m];
+    } else {
+      if (!(t < t_end) || steps >= max_steps || bad) break;
+      dt = cfl / qmax;
+      if (dt > t_end - t) dt = t_end - t;
+    }
+    const T c1 = (T)((0.5 * dt) * M.inv_dx[0]);
+    const T c2 = (T)(dt * M.inv_dx[0]);
+    resident_stage<T>(M, g, n, c1, u, u, u1, sV, sF);
+    resident_stage<T>(M, g, n, c2, u1, u, u, sV, sF);
+    t += dt;
+    ++steps;
+    if (!explicit_dt) {
+      double q = 0.0;
+      bool b = false;
+#pragma unroll
+      for (int r = 0; r < kResidentPerThread; ++r) {
+        const int i = tid + r * kResidentThreads;
+        if (i < n) {
+          const double qi = cfl_q<T, 1>(u[r], M.inv_dx, M.gamma);
+          b |= !(qi > 0.0);
+          q = fmax(q, qi);
+        }
+      }
+      // the block maximum (thread 0) and the non-physical flag reach every thread through LDS
+      const double bm = block_max(b ? -1.0 : q, s_red);
+      __syncthreads();
+      if (tid == 0) s_red[0] = bm;
+      if (tid == 0) s_bad = 0;
+      __syncthreads();
+      if (b) s_bad = 1;
+      __syncthreads();
+      qmax = s_red[0];
+      bad = s_bad != 0;
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kResidentPerThread; ++r) {
+    const int i = tid + r * kResidentThreads;
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) Uout.f[q][i] = u[r][q];
+    }
+  }
+  if (m == 0 && tid < 16 && a.queue) a.queue[((a.ring + 2) % 3) * 16 + tid] = 0u;
+  if (!explicit_dt && tid == 0) {
+    const int nx = (a.ring + 1) % 3, nn = (a.ring + 2) % 3;
+    c.t[nx] = t;
+    c.steps[nx] = steps;
+    c.qbits[nx] = (unsigned long long)__double_as_longlong(qmax);
+    c.qbits[nn] = 0ull;
+    if (bad) c.flags |= 1;
+  }
+}
+
+}  // namespace paraiso

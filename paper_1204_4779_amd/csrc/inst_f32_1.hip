@@ -1,5 +1,6 @@
 // Kernel instantiations for float, 1D.
 #include "euler_kernels.h"
+#include "euler_resident1d.h"
 #include "kernel_table.h"
 
 namespace paraiso {
@@ -16,6 +17,7 @@ const KernelTable* table_f32_1() {
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      (const void*)k_resident1d<float>,
       (const void*)k_cfl<float, 1>,
       (const void*)k_totals_partial<float, 1>,
       (const void*)k_totals_final<1>,

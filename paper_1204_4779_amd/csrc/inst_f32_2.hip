@@ -19,6 +19,7 @@ const KernelTable* table_f32_2() {
       {(const void*)k_march2d<float, 0, false>, (const void*)k_march2d<float, 3, false>,
        (const void*)k_march2d<float, 4, false>, (const void*)k_march2d<float, 5, false>},
       {nullptr, nullptr, nullptr, nullptr},
+      nullptr,
       (const void*)k_cfl<float, 2>,
       (const void*)k_totals_partial<float, 2>,
       (const void*)k_totals_final<2>,

@@ -19,6 +19,7 @@ const KernelTable* table_f64_2() {
       {(const void*)k_march2d<double, 0, false>, (const void*)k_march2d<double, 3, false>,
        (const void*)k_march2d<double, 4, false>, (const void*)k_march2d<double, 5, false>},
       {nullptr, nullptr, nullptr, nullptr},
+      nullptr,
       (const void*)k_cfl<double, 2>,
       (const void*)k_totals_partial<double, 2>,
       (const void*)k_totals_final<2>,

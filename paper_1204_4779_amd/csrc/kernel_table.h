@@ -14,6 +14,7 @@ struct KernelTable {
   const void* march_fused[4];  // 2D register march (null for other dimensions)
   const void* march_stage[4];
   const void* march3d_stage[4];  // 3D register march, one stage (null for other dimensions)
+  const void* resident1d;        // whole-advance kernel of small 1D meshes (null otherwise)
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "euler_kernels.h"
+#include "euler_resident1d.h"
 #include "kernel_table.h"
 #include "paraiso.h"
 
@@ -163,7 +164,7 @@ struct paraiso_ctx {
   double* d_partials = nullptr;
   const KernelTable* tab = nullptr;
   paraiso_variant var{};
-  bool fused = false, lds = false, persistent = false;
+  bool fused = false, lds = false, persistent = false, resident = false;
   int nitems = 0;
   int xcd_begin[9] = {};
   LdsGeom geom{};
@@ -222,7 +223,7 @@ int enqueue_step(const paraiso_ctx* c, int cur, int ring, bool explicit_dt, hipS
   a.dt = explicit_dt ? c->d_dt : nullptr;
   a.src = cur;
   a.ring = ring;
-  if (c->fused) {
+  if (c->fused || c->resident) {
     a.stage = 0;
     a.cfl = explicit_dt ? 0 : 1;
     return launch(c->step, a, c->geom, s);
@@ -307,7 +308,17 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
       return PARAISO_ERR_UNSUPPORTED;
     }
   }
-  if (v.lds < 0 || v.lds > 2) return why = "lds must be 0, 1 or 2", PARAISO_ERR_UNSUPPORTED;
+  if (v.lds < 0 || v.lds > 3) return why = "lds must be 0, 1, 2 or 3", PARAISO_ERR_UNSUPPORTED;
+  if (v.lds == 3) {
+    if (d != 1) return why = "resident kernel (lds = 3) exists for 1D meshes only", PARAISO_ERR_UNSUPPORTED;
+    for (const auto& m : c->meshes) {
+      if (m.n[0] > kResidentCells)
+        return why = "resident kernel: at most " + std::to_string(kResidentCells) + " cells per mesh",
+               PARAISO_ERR_UNSUPPORTED;
+      if ((size_t)c->esize * (6 * (size_t)m.n[0] + 3) + 256 > (size_t)c->max_lds)
+        return why = "resident kernel: mesh does not fit in LDS", PARAISO_ERR_UNSUPPORTED;
+    }
+  }
   if (v.lds == 2) {
     if (d == 1) return why = "register march (lds = 2) exists for 2D and 3D meshes", PARAISO_ERR_UNSUPPORTED;
     if (v.tile[0] != 64) return why = "register march: tile[0] must be 64 (one wave of columns)", PARAISO_ERR_UNSUPPORTED;
@@ -342,7 +353,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   int rc = validate_variant(c, v, why);
   if (rc) return fail(rc, "variant: " + why);
   const int d = c->ndim, nf = d + 2;
-  const int threads = (v.lds == 2 && d == 3) ? 64 * v.tile[1] : (v.threads ? v.threads : 256);
+  const int threads = v.lds == 3 ? kResidentThreads
+                      : (v.lds == 2 && d == 3) ? 64 * v.tile[1] : (v.threads ? v.threads : 256);
   // tile of one work item: the variant's tile, or for the register march
   // (64 - 2H) columns by rows-per-wave times waves-per-block
   int et[3] = {v.tile[0], v.tile[1], v.tile[2]};
@@ -396,6 +408,11 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   }
   G.vstride = G.vin.count;
   G.fstride = fmax_count;
+  if (v.lds == 3) {
+    int64_t nmax = 1;
+    for (const auto& m : c->meshes) nmax = std::max<int64_t>(nmax, m.n[0]);
+    shmem = (size_t)c->esize * (6 * (size_t)nmax + 3);
+  }
   if (v.lds == 2 && d == 3) {
     const int nw = v.tile[1];
     shmem = (size_t)c->esize * 5 * 64 * (2 * (size_t)(nw + 4) + 3 * (size_t)(nw + 1));
@@ -416,7 +433,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   // periodic wrap; nothing else to check
   const int ws = waves_slot(v.waves_per_eu);
   Launch L;
-  if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
+  if (v.lds == 3) L.fn = c->tab->resident1d;
+  else if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
   else if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
   else if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
   else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
@@ -434,6 +452,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
     grid = std::min<int64_t>((int64_t)per_cu * c->num_cus, nitems);
     grid = std::max(grid, 1);
   }
+  if (v.lds == 3) grid = c->count;
   L.grid = dim3(grid);
   {
     hipFuncAttributes fa{};
@@ -451,9 +470,16 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   v.threads = threads;
   c->var = v;
   for (int a = 0; a < 3; ++a) c->eff_tile[a] = et[a];
+  // kernels of different variants keep the work-queue ring differently: start clean
+  {
+    int rc2 = ctl_init(c, nullptr);
+    if (rc2) return rc2;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
   c->fused = v.fuse != 0;
   c->lds = v.lds != 0;
   c->persistent = v.persistent != 0;
+  c->resident = v.lds == 3;
   c->nitems = nitems;
   c->geom = G;
   c->step = L;
@@ -661,6 +687,22 @@ int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_st
   if (!rc) rc = launch_cfl(c);
   if (rc) return rc;
   std::vector<Ctl> h(c->count);
+  if (c->resident) {
+    // the whole advance in one launch; it counts as one buffer flip
+    rc = enqueue_step(c, c->cur, c->ring, false, c->stream);
+    if (rc) return rc;
+    c->cur ^= 1;
+    c->ring = (c->ring + 1) % 3;
+    HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int m = 0; m < c->count; ++m) {
+      t_inout[m] = h[m].t[c->ring];
+      steps_out[m] = h[m].steps[c->ring];
+    }
+    for (int m = 0; m < c->count; ++m)
+      if (h[m].flags) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": non-physical state");
+    return PARAISO_OK;
+  }
   std::vector<double> t0(t_inout, t_inout + c->count);
   int64_t launched = 0;
   int64_t chunk = std::isinf(t_end) ? max_steps : std::min<int64_t>(max_steps, 32);

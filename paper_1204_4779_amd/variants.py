@@ -17,7 +17,8 @@ TUNED = {
     ("box256", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=0),
     ("box512", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=0),
     ("batch512", "f32"): dict(tile=(64, 16), lds=2, fuse=1, waves_per_eu=0, threads=256, persistent=1),
-    ("sod1024", "f64"): dict(tile=(256,), lds=1, fuse=1, waves_per_eu=0, threads=256),
+    # the whole advance in one launch, one workgroup holding the 1024 cells
+    ("sod1024", "f64"): dict(tile=(1024,), lds=3, fuse=1),
 }
 
 

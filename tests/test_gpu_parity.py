@@ -318,3 +318,64 @@ def test_graph_replays_interleaved_with_eager_work(vname):
         g.step(dt)
         e.step(dt)
         assert g.totals() == e.totals()
+
+
+# the largest mesh the resident kernel holds: 4096 cells in FP32; in FP64 the
+# primitive and flux planes (8 * (6n + 3) bytes) cap it at 3407 cells of 160 KiB LDS
+RESIDENT_MAX = {"f32": 4096, "f64": 3407}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [0, 1])
+@pytest.mark.parametrize("n", [1, 3, 203, 1024, "max"])
+def test_resident_1d_step_matches_oracle(dtype, bc, n):
+    n = RESIDENT_MAX[dtype] if n == "max" else n
+    pr = inputs.random_state(1, (n,), seed=500 + n + bc, rough=True, bc=(bc,))
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.5)
+    ref = oracle.step(m, U0, dt)
+    s = gpu_solver(spec_of(pr), dtype, dict(tile=(n,), lds=3, fuse=1), pr.U)
+    s.step(dt)
+    assert rel_err(gpu_state(s), ref) <= TOL[dtype]
+
+
+def test_resident_1d_sod_advance_and_batch():
+    from oracle import exact_riemann as er
+    pr = inputs.sod_1d(1024)
+    ref, t_ref, steps_ref = oracle.advance(oracle_mesh(pr), pr.U, 0.5, 0.2)
+    s = gpu_solver(spec_of(pr), "f64", dict(tile=(1024,), lds=3, fuse=1), pr.U)
+    t, steps = s.advance(0.2, 0.5)
+    assert t[0] == 0.2 and steps[0] == steps_ref
+    assert rel_err(gpu_state(s), ref) < 1e-10
+    # a batch of 1D meshes, one block each, different step counts
+    probs = [inputs.sod_1d(n) for n in (256, 1000, 64)]
+    b = gpu_solver([spec_of(p) for p in probs], "f64", dict(tile=(1024,), lds=3, fuse=1), [p.U for p in probs])
+    tb, nb = b.advance(0.1, 0.5, t0=[0.0] * 3)
+    for k, p in enumerate(probs):
+        r, tr, nr = oracle.advance(oracle_mesh(p), p.U, 0.5, 0.1)
+        assert nb[k] == nr and tb[k] == tr
+        assert rel_err(gpu_state(b, k), r) < 1e-10
+    # switching to a queue-driven persistent variant afterwards still covers every tile
+    b.set_variant(dict(tile=(64,), lds=1, fuse=1, persistent=1))
+    dts = [1e-4] * 3
+    refs = [oracle.step(oracle_mesh(p), gpu_state(b, k), 1e-4) for k, p in enumerate(probs)]
+    b.step(dts)
+    for k in range(3):
+        assert rel_err(gpu_state(b, k), refs[k]) < 1e-12
+
+
+def test_resident_1d_rejects_large_and_2d():
+    pr = inputs.random_state(1, (5000,), seed=1)
+    s = gpu_solver(spec_of(pr), "f64", None, pr.U)
+    with pytest.raises(pb.ParaisoError):
+        s.set_variant(dict(tile=(5000,), lds=3, fuse=1))
+    # one cell past the FP64 LDS limit
+    pr1 = inputs.random_state(1, (RESIDENT_MAX["f64"] + 1,), seed=1)
+    s1 = gpu_solver(spec_of(pr1), "f64", None, pr1.U)
+    with pytest.raises(pb.ParaisoError):
+        s1.set_variant(dict(tile=(RESIDENT_MAX["f64"] + 1,), lds=3, fuse=1))
+    pr2 = inputs.random_state(2, (16, 16), seed=1)
+    s2 = gpu_solver(spec_of(pr2), "f64", None, pr2.U)
+    with pytest.raises(pb.ParaisoError):
+        s2.set_variant(dict(tile=(16, 16), lds=3, fuse=1))
