@@ -92,10 +92,27 @@ struct Fp<float> {
 
 template <>
 struct Fp<double> {
-  static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-  static __device__ __forceinline__ double sqrt(double x) { return ::sqrt(x); }
-  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
-  static __device__ __forceinline__ double sqrt_ratio(double a, double b) { return ::sqrt(a / b); }
+  // The hardware seeds (v_rcp_f64, v_rsq_f64) refined by two Newton-Raphson
+  // steps each; every step squares the relative error of the seed, leaving a
+  // result within a few ulp.  The FP64 path is held to a relative error
+  // budget of 1e-12 per step, not to correct rounding, and this costs about
+  // half of the IEEE division and square-root sequences.  Arguments are
+  // positive normal numbers on physical states; anything else yields a
+  // non-finite value, which the CFL check reports.
+  static __device__ __forceinline__ double rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+  }
+  static __device__ __forceinline__ double rsqrt(double x) {
+    const double h = 0.5 * x;
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+  }
+  static __device__ __forceinline__ double div(double a, double b) { return a * rcp(b); }
+  // sqrt(a / b) for a, b > 0: a * rsqrt(a b)
+  static __device__ __forceinline__ double sqrt_ratio(double a, double b) { return a * rsqrt(a * b); }
   static __device__ __forceinline__ double med0(double a, double b) {
     return fmax(fmin(a, b), fmin(fmax(a, b), 0.0));
   }
@@ -220,7 +237,7 @@ __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double
 #pragma unroll
   for (int q = 0; q < D + 2; ++q) ud[q] = (double)u[q];
   const double rho = ud[0];
-  const double ir = 1.0 / rho;
+  const double ir = Fp<double>::rcp(rho);
   double ke = 0.0;
   double vel[D];
 #pragma unroll
@@ -229,7 +246,7 @@ __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double
     ke += vel[a] * ud[1 + a];
   }
   const double p = (gamma - 1.0) * (ud[D + 1] - 0.5 * ke);
-  const double cs = ::sqrt(gamma * p * ir);
+  const double cs = Fp<double>::sqrt_ratio(gamma * p, rho);
   double q = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) q += (fabs(vel[a]) + cs) * inv_dx[a];

@@ -67,25 +67,25 @@ struct RowPipe {
   T g[4];        // y-face flux between rows k-3 and k-2
 };
 
-// Push V(row k) as `c`; with `n` rows pushed before this one.  When n >= 4
-// the update acc = kx dFx + ky dGy of row k-2 is returned in acc and the
-// function returns true.
-template <typename T>
-__device__ __forceinline__ bool pipe_push(RowPipe<T>& P, const T* c, int n, const Gas<T>& g, T kx, T ky,
-                                          T* acc) {
-  bool done = false;
-  if (n >= 2) {
-    T slope[4], lo_b[4], up_b[4];
+// Push V(row k) as `c` into a stage pipeline that has received N rows
+// before this one (N = 4 stands for 4 or more: the steady state; N = -1
+// takes the count from n at run time).  When the count is 4 or more the
+// update acc = kx dFx + ky dGy of row k-2 is written to acc.
+template <typename T, int N>
+__device__ __forceinline__ void pipe_push(RowPipe<T>& P, const T* c, const Gas<T>& g, T kx, T ky, T* acc,
+                                          int n = N) {
+  if (N >= 2 || (N < 0 && n >= 2)) {
+    T lo_b[4], up_b[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      slope[q] = minmod(P.b[q] - P.a[q], c[q] - P.b[q]);
-      lo_b[q] = P.b[q] - T(0.5) * slope[q];
-      up_b[q] = P.b[q] + T(0.5) * slope[q];
+      const T slope = minmod(P.b[q] - P.a[q], c[q] - P.b[q]);
+      lo_b[q] = P.b[q] - T(0.5) * slope;
+      up_b[q] = P.b[q] + T(0.5) * slope;
     }
-    if (n >= 3) {
+    if (N >= 3 || (N < 0 && n >= 3)) {
       T G[4];
       hllc<T, 2, 1>(P.upa, lo_b, G, g);
-      if (n >= 4) {
+      if (N >= 4 || (N < 0 && n >= 4)) {
         T dF[4];
         xflux_diff<T>(P.a, g, dF);
 #pragma unroll
@@ -93,7 +93,6 @@ __device__ __forceinline__ bool pipe_push(RowPipe<T>& P, const T* c, int n, cons
           acc[q] = kx * dF[q];
           acc[q] += ky * (P.g[q] - G[q]);
         }
-        done = true;
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) P.g[q] = G[q];
@@ -106,8 +105,145 @@ __device__ __forceinline__ bool pipe_push(RowPipe<T>& P, const T* c, int n, cons
     P.a[q] = P.b[q];
     P.b[q] = c[q];
   }
-  return done;
 }
+
+// State of one wave marching one strip of one work item.  The y-windows
+// (two stage pipelines, the base-state ring ub and the prefetched row) are
+// shifted by plain assignments every push; the caller unrolls the steady
+// state six-fold, so that after inlining the shifts are register renames
+// and the loop carries no copies (every ring period divides six).
+template <typename T, bool FUSED>
+struct StripMarch {
+  Fields<T, 2> U0, Uin, Uout;
+  Gas<T> g;
+  T kx1, ky1, kx2, ky2;
+  const double* inv_dx;
+  double gamma;
+  int nx, ny, first, bcy;
+  unsigned col;
+  bool base_is_input;  // the stage's base state is its input (fused step, stage 1)
+  bool cfl, store_lane;  // cfl: fold the CFL quantity of every stored cell
+  RowPipe<T> P1, P2;
+  T ub[5][4];  // base state of rows k-4 .. k
+  T nxt[4];    // input row k+1, loaded one push ahead
+  double qmax;
+  bool bad;
+
+  // Row offsets are wave-uniform (scalar registers) and the column a 32-bit
+  // unsigned byte offset per lane, so each access is one global load or
+  // store with a scalar base and no per-lane 64-bit address arithmetic.
+  // (The empty asm keeps the offset from being folded into hoisted 64-bit
+  // lane addresses by loop-invariant code motion.)
+  __device__ __forceinline__ unsigned lane_bytes() const {
+    unsigned c = col * (unsigned)sizeof(T);
+    asm volatile("" : "+v"(c));
+    return c;
+  }
+  static __device__ __forceinline__ __attribute__((address_space(1))) T* at(
+      __attribute__((address_space(1))) T* row, unsigned bytes) {
+    return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)row + bytes);
+  }
+
+  __device__ __forceinline__ void load_row(int k, T* u) const {
+    const int ro = map_index(first + k, ny, bcy) * nx;
+    const unsigned c = lane_bytes();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = *at(Uin.f[q] + ro, c);
+  }
+
+  __device__ __forceinline__ void emit(int y, const T* u) {
+    const int ro = y * nx;
+    if (store_lane) {
+      const unsigned c = lane_bytes();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) *at(Uout.f[q] + ro, c) = u[q];
+      if (cfl) {
+        const double qv = cfl_q<T, 2>(u, inv_dx, gamma);
+        bad |= !(qv > 0.0);
+        qmax = fmax(qmax, qv);
+      }
+    }
+  }
+
+  // Row k enters stage 1, which has received S1 rows before it (4: four or
+  // more); in the fused step a completed stage-1 row enters stage 2, which
+  // has received S2 rows before it.
+  template <int S1, int S2>
+  __device__ __forceinline__ void push(int k, int n2 = S2) {
+    T u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = nxt[q];
+    load_row(k + 1, nxt);  // in range for any k (wrapped or clamped); unused after the last row
+    T base[4];
+    if (base_is_input) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) base[q] = u[q];
+    } else {
+      const int ro = map_index(first + k, ny, bcy) * nx;
+      const unsigned c = lane_bytes();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) base[q] = *at(U0.f[q] + ro, c);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ub[s][q] = ub[s + 1][q];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ub[4][q] = base[q];
+    T v[4];
+    prim_of_cons<T, 2>(u, v, g);
+    T acc[4];
+    pipe_push<T, S1>(P1, v, g, kx1, ky1, acc);
+    if constexpr (S1 >= 4) {
+      // stage-1 output: row first + k - 2, base ub[2]
+      T u1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u1[q] = ub[2][q] + acc[q];
+      if constexpr (!FUSED) {
+        emit(first + k - 2, u1);
+      } else {
+        T v1[4];
+        prim_of_cons<T, 2>(u1, v1, g);
+        T acc2[4];
+        pipe_push<T, S2>(P2, v1, g, kx2, ky2, acc2, n2);
+        if constexpr (S2 >= 4) {
+          // stage-2 output: row first + k - 4, base ub[0]
+          T u2[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) u2[q] = ub[0][q] + acc2[q];
+          emit(first + k - 4, u2);
+        }
+      }
+    }
+  }
+
+  // all rows of the strip: npush = output rows + 2H
+  __device__ __forceinline__ void run(int npush) {
+    load_row(0, nxt);
+    int k = 0;
+    // stage-1 warm-up (cheap pushes, straight-line code)
+    push<0, 0>(k++);
+    push<1, 0>(k++);
+    push<2, 0>(k++);
+    push<3, 0>(k++);
+    // stage-2 warm-up of the fused step as a loop: as straight-line code
+    // the compiler overlaps these four pushes and needs ~50 more VGPRs
+    if constexpr (FUSED) {
+#pragma clang loop unroll(disable)
+      for (int n2 = 0; n2 < 4; ++n2) push<4, -1>(k++, n2);
+    }
+    // steady state, unrolled six-fold
+    for (; k + 6 <= npush; k += 6) {
+      push<4, 4>(k);
+      push<4, 4>(k + 1);
+      push<4, 4>(k + 2);
+      push<4, 4>(k + 3);
+      push<4, 4>(k + 4);
+      push<4, 4>(k + 5);
+    }
+    for (; k < npush; ++k) push<4, 4>(k);
+  }
+};
 
 // Fused step (FUSED, periodic meshes) or one stage (!FUSED, periodic or
 // outflow: the stage's ghost cells are clamped loads of its input).
@@ -119,29 +255,29 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
   __shared__ double s_red[16];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // wave-uniform, so the row loop is scalar control flow
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int rows = a.tile[1] / (blockDim.x >> 6);
   ItemLoop it{0, 1};
   for (int item; (item = next_item(a, it, &s_item, FUSED ? 0 : a.stage - 1)) >= 0;) {
+    item = __builtin_amdgcn_readfirstlane(item);  // the same for the whole block
     const Tile t = tile_of(a, item);
     const MeshDev& M = a.meshes[t.m];
     bool active;
     const double dt = step_dt(a, t.m, active);
     const bool last_stage = FUSED || a.stage == 2;
     if (last_stage && t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
-    const Gas<T> g = gas_of<T>(M);
     const int nx = M.n[0], ny = M.n[1];
     const int x0 = t.org[0], y0 = t.org[1] + wave * rows;
     const int y1 = min(y0 + rows, ny);
     const int col = map_index(x0 - H + lane, nx, FUSED ? kPeriodic : M.bc[0]);
     const bool store_lane = lane >= H && lane < 64 - H && (x0 - H + lane) < nx;
     const Fields<T, 2> U0 = fields<T, 2>(M.s[a.src]);
-    const Fields<T, 2> Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
-    const Fields<T, 2> Uout =
-        (FUSED || a.stage == 2) ? fields<T, 2>(M.s[1 - a.src]) : fields<T, 2>(M.w);
     double qmax = 0.0;
     bool bad = false;
     if (y0 < ny && (active || last_stage)) {
+      const Fields<T, 2> Uout =
+          (FUSED || a.stage == 2) ? fields<T, 2>(M.s[1 - a.src]) : fields<T, 2>(M.w);
       if (!active) {
         for (int y = y0; y < y1; ++y) {
           const int gi = y * nx + col;
@@ -150,90 +286,31 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
             if (store_lane) Uout.f[q][gi] = U0.f[q][gi];
         }
       } else {
+        StripMarch<T, FUSED> S;
+        S.U0 = U0;
+        S.Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
+        S.Uout = Uout;
+        S.g = gas_of<T>(M);
         const double c1 = FUSED ? 0.5 * dt : (a.stage == 1 ? 0.5 * dt : dt);
-        const T kx1 = (T)(c1 * M.inv_dx[0]), ky1 = (T)(c1 * M.inv_dx[1]);
-        const T kx2 = (T)(dt * M.inv_dx[0]), ky2 = (T)(dt * M.inv_dx[1]);
-        RowPipe<T> P1, P2;
-        // base-state ring: U0 of the rows whose update is pending
-        T ub[5][4];
-        const int first = y0 - H;          // first row pushed into stage 1
-        const int npush = (y1 - y0) + 2 * H;
-        int n1 = 0, n2 = 0;
-        T nxt[4];
-        {
-          const int gi = map_index(first, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) nxt[q] = Uin.f[q][gi];
-        }
-        for (int k = 0; k < npush; ++k) {
-          T u[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) u[q] = nxt[q];
-          if (k + 1 < npush) {
-            const int gi = map_index(first + k + 1, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) nxt[q] = Uin.f[q][gi];
-          }
-          // base state of this row (U0; equals u for the fused step and stage 1)
-          T base[4];
-          if (FUSED || a.stage == 1) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) base[q] = u[q];
-          } else {
-            const int gi = map_index(first + k, ny, FUSED ? kPeriodic : M.bc[1]) * nx + col;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) base[q] = U0.f[q][gi];
-          }
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) ub[s][q] = ub[s + 1][q];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) ub[4][q] = base[q];
-          T v[4];
-          prim_of_cons<T, 2>(u, v, g);
-          T acc[4];
-          if (pipe_push<T>(P1, v, n1++, g, kx1, ky1, acc)) {
-            // stage-1 output: row first + k - 2, its base is ub[2]
-            T u1[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) u1[q] = ub[2][q] + acc[q];
-            if (!FUSED) {
-              const int y = first + k - 2;
-              const int gi = y * nx + col;
-              if (store_lane) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Uout.f[q][gi] = u1[q];
-              }
-              if (last_stage && a.cfl && store_lane) {
-                const double qv = cfl_q<T, 2>(u1, M.inv_dx, M.gamma);
-                bad |= !(qv > 0.0);
-                qmax = fmax(qmax, qv);
-              }
-            } else {
-              T v1[4];
-              prim_of_cons<T, 2>(u1, v1, g);
-              T acc2[4];
-              if (pipe_push<T>(P2, v1, n2++, g, kx2, ky2, acc2)) {
-                // stage-2 output: row first + k - 4, base ub[0]
-                const int y = first + k - 4;
-                T u2[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) u2[q] = ub[0][q] + acc2[q];
-                const int gi = y * nx + col;
-                if (store_lane) {
-#pragma unroll
-                  for (int q = 0; q < 4; ++q) Uout.f[q][gi] = u2[q];
-                }
-                if (a.cfl && store_lane) {
-                  const double qv = cfl_q<T, 2>(u2, M.inv_dx, M.gamma);
-                  bad |= !(qv > 0.0);
-                  qmax = fmax(qmax, qv);
-                }
-              }
-            }
-          }
-        }
+        S.kx1 = (T)(c1 * M.inv_dx[0]);
+        S.ky1 = (T)(c1 * M.inv_dx[1]);
+        S.kx2 = (T)(dt * M.inv_dx[0]);
+        S.ky2 = (T)(dt * M.inv_dx[1]);
+        S.inv_dx = M.inv_dx;
+        S.gamma = M.gamma;
+        S.nx = nx;
+        S.ny = ny;
+        S.col = (unsigned)col;
+        S.first = y0 - H;
+        S.bcy = FUSED ? kPeriodic : M.bc[1];
+        S.base_is_input = FUSED || a.stage == 1;
+        S.cfl = a.cfl != 0 && last_stage;
+        S.store_lane = store_lane;
+        S.qmax = 0.0;
+        S.bad = false;
+        S.run((y1 - y0) + 2 * H);
+        qmax = S.qmax;
+        bad = S.bad;
       }
     }
     if (a.cfl && active && last_stage) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);

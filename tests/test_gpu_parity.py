@@ -222,7 +222,9 @@ def test_register_march_matches_oracle(dtype, fuse, n):
     m = oracle_mesh(pr)
     dt = oracle.cfl_dt(m, U0, 0.5)
     ref = oracle.step(m, U0, dt)
-    for rows, threads in ((8, 256), (16, 64), (64, 128)):
+    # rows per wave: a steady state shorter than, equal to and longer than
+    # the six-push unrolled group, with and without a remainder
+    for rows, threads in ((8, 256), (16, 64), (64, 128), (6, 192), (25, 256)):
         v = dict(tile=(64, rows), lds=2, fuse=fuse, threads=threads)
         s = gpu_solver(spec_of(pr), dtype, v, pr.U)
         s.step(dt)
