@@ -230,7 +230,10 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
 }
 
 // CFL quantity sum_a (|v_a| + c)/dx_a of one cell, in FP64; returns a
-// negative value for a non-physical or non-finite state.
+// negative value for a non-physical or non-finite state.  With rho > 0,
+// every other failure (p <= 0, a NaN or infinite component) makes q NaN on
+// its way through the reciprocal square root of gamma p rho, so one test
+// for rho > 0 and one for q < inf cover them all.
 template <typename T, int D>
 __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double gamma) {
   double ud[D + 2];
@@ -250,7 +253,7 @@ __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double
   double q = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) q += (fabs(vel[a]) + cs) * inv_dx[a];
-  const bool ok = (rho > 0.0) && (p > 0.0) && isfinite(q) && isfinite(ud[D + 1]);
+  const bool ok = (rho > 0.0) && (q < __builtin_huge_val());
   return ok ? q : -1.0;
 }
 

@@ -216,6 +216,7 @@ struct LdsGeom {
   int halo;     // H: 4 fused, 2 unfused
   int vstride;  // fields stride in the V region (elements)
   int fstride;  // fields stride in the flux buffer
+  int rows;     // 2D register march: rows per wave
 };
 
 template <typename T, int D>

@@ -20,6 +20,22 @@
 
 namespace paraiso {
 
+// Fused step, rows shared between the waves of a block.  The waves of a
+// block are stacked along y.  Wave w computes stage 1 on its own rows only
+// (input rows from 2 above to 2 below them) and its stage-2 outputs are
+// shifted down by two rows: rows [y0 + 2, y1 + 2) of its range [y0, y1).
+// The four stage-1 rows below its range are the first four stage-1 rows of
+// wave w + 1, which that wave leaves in LDS; only the last wave of a block
+// computes them itself.  Two rows of stage-1 recomputation per wave instead
+// of four per side, one barrier per work item, and the last wave, which has
+// the extra work, takes two rows fewer.  With one wave per block, or fewer
+// than 6 rows per wave, every wave works as a last wave.
+__host__ __device__ constexpr bool march2d_shares(int nwaves, int rows) { return nwaves > 1 && rows >= 6; }
+// Rows of one work item of the fused march.
+__host__ __device__ constexpr int march2d_item_rows(int nwaves, int rows) {
+  return nwaves * rows - (march2d_shares(nwaves, rows) ? 2 : 0);
+}
+
 // lane l receives lane l-1 (lane 0 receives 0)
 __device__ __forceinline__ float lane_from_left(float x) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
@@ -117,7 +133,7 @@ struct StripMarch {
   Fields<T, 2> U0, Uin, Uout;
   Gas<T> g;
   T kx1, ky1, kx2, ky2;
-  const double* inv_dx;
+  double inv_dx[2];  // held in registers: the CFL epilogue reads them every row
   double gamma;
   int nx, ny, first, bcy;
   unsigned col;
@@ -128,6 +144,12 @@ struct StripMarch {
   T nxt[4];    // input row k+1, loaded one push ahead
   double qmax;
   bool bad;
+  // fused step: this wave's first four stage-1 rows for the wave above
+  // (null: not needed) and the next wave's, read at the end (null: this wave
+  // computes the four rows below its range itself); [row][field][lane]
+  T* share_out;
+  const T* share_in;
+  int lane;
 
   // Row offsets are wave-uniform (scalar registers) and the column a 32-bit
   // unsigned byte offset per lane, so each access is one global load or
@@ -152,7 +174,8 @@ struct StripMarch {
   }
 
   __device__ __forceinline__ void emit(int y, const T* u) {
-    const int ro = y * nx;
+    // the fused step's outputs are shifted by two rows and wrap (periodic)
+    const int ro = (FUSED ? map_index(y, ny, kPeriodic) : y) * nx;
     if (store_lane) {
       const unsigned c = lane_bytes();
 #pragma unroll
@@ -160,7 +183,7 @@ struct StripMarch {
       if (cfl) {
         const double qv = cfl_q<T, 2>(u, inv_dx, gamma);
         bad |= !(qv > 0.0);
-        qmax = fmax(qmax, qv);
+        qmax = qv > qmax ? qv : qmax;
       }
     }
   }
@@ -169,7 +192,7 @@ struct StripMarch {
   // more); in the fused step a completed stage-1 row enters stage 2, which
   // has received S2 rows before it.
   template <int S1, int S2>
-  __device__ __forceinline__ void push(int k, int n2 = S2) {
+  __device__ __forceinline__ void push(int k, int n2 = S2, T* v1_out = nullptr) {
     T u[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) u[q] = nxt[q];
@@ -204,6 +227,10 @@ struct StripMarch {
       } else {
         T v1[4];
         prim_of_cons<T, 2>(u1, v1, g);
+        if (v1_out) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v1_out[q * 64 + lane] = v1[q];
+        }
         T acc2[4];
         pipe_push<T, S2>(P2, v1, g, kx2, ky2, acc2, n2);
         if constexpr (S2 >= 4) {
@@ -217,8 +244,28 @@ struct StripMarch {
     }
   }
 
-  // all rows of the strip: npush = output rows + 2H
-  __device__ __forceinline__ void run(int npush) {
+  // Stage 2 only: push a stage-1 row of the next wave (from LDS).
+  __device__ __forceinline__ void push_shared(int k, const T* row) {
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) ub[s][q] = ub[s + 1][q];
+    T v1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v1[q] = row[q * 64 + lane];
+    T acc2[4];
+    pipe_push<T, 4>(P2, v1, g, kx2, ky2, acc2);
+    T u2[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u2[q] = ub[0][q] + acc2[q];
+    emit(first + k - 4, u2);
+  }
+
+  // All rows of the strip: npush stage-1 pushes (output rows + 4, + 4 more
+  // for a fused-step wave that computes the rows below its range itself).
+  // `barrier`: the block shares rows; every wave of the block, active or
+  // not, passes one barrier per work item.
+  __device__ __forceinline__ void run(int npush, bool barrier) {
     load_row(0, nxt);
     int k = 0;
     // stage-1 warm-up (cheap pushes, straight-line code)
@@ -226,11 +273,13 @@ struct StripMarch {
     push<1, 0>(k++);
     push<2, 0>(k++);
     push<3, 0>(k++);
-    // stage-2 warm-up of the fused step as a loop: as straight-line code
-    // the compiler overlaps these four pushes and needs ~50 more VGPRs
     if constexpr (FUSED) {
+      // stage-2 warm-up as a loop: as straight-line code the compiler
+      // overlaps these four pushes and needs ~50 more VGPRs.  Their stage-1
+      // rows are this wave's first four.
 #pragma clang loop unroll(disable)
-      for (int n2 = 0; n2 < 4; ++n2) push<4, -1>(k++, n2);
+      for (int n2 = 0; n2 < 4; ++n2) push<4, -1>(k++, n2, share_out ? share_out + n2 * 256 : nullptr);
+      if (barrier) __syncthreads();
     }
     // steady state, unrolled six-fold
     for (; k + 6 <= npush; k += 6) {
@@ -242,22 +291,34 @@ struct StripMarch {
       push<4, 4>(k + 5);
     }
     for (; k < npush; ++k) push<4, 4>(k);
+    if constexpr (FUSED) {
+      if (share_in) {
+#pragma clang loop unroll(disable)
+        for (int j = 0; j < 4; ++j) push_shared(k++, share_in + j * 256);
+      }
+    }
   }
 };
 
 // Fused step (FUSED, periodic meshes) or one stage (!FUSED, periodic or
 // outflow: the stage's ghost cells are clamped loads of its input).
-// Block = threads/64 waves; the block tile is (64 - 2H) columns by
-// (waves * rows) rows, wave w taking rows [w*rows, (w+1)*rows) of it.
+// Block = threads/64 waves stacked along y, `rows` rows each: the block
+// tile is (64 - 2H) columns by march2d_item_rows(waves, rows) rows (the
+// last wave of a sharing block takes rows - 2).
 template <typename T, int W, bool FUSED>
-__global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, LdsGeom) {
+__global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, LdsGeom G) {
   constexpr int H = FUSED ? 4 : 2;
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
   // wave-uniform, so the row loop is scalar control flow
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int rows = a.tile[1] / (blockDim.x >> 6);
+  const int nwaves = blockDim.x >> 6;
+  const int rows = G.rows;
+  const bool share = FUSED && march2d_shares(nwaves, rows);
+  const int item_rows = FUSED ? march2d_item_rows(nwaves, rows) : rows * nwaves;
+  T* const lds_rows = reinterpret_cast<T*>(smem);  // [wave][4 rows][4 fields][64 lanes]
   ItemLoop it{0, 1};
   for (int item; (item = next_item(a, it, &s_item, FUSED ? 0 : a.stage - 1)) >= 0;) {
     item = __builtin_amdgcn_readfirstlane(item);  // the same for the whole block
@@ -268,50 +329,62 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
     const bool last_stage = FUSED || a.stage == 2;
     if (last_stage && t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
     const int nx = M.n[0], ny = M.n[1];
-    const int x0 = t.org[0], y0 = t.org[1] + wave * rows;
-    const int y1 = min(y0 + rows, ny);
+    const int x0 = t.org[0];
+    const int yb1 = min(t.org[1] + item_rows, ny);  // end of the block's rows
+    const int y0 = t.org[1] + wave * rows;
+    const int y1 = min(y0 + rows, yb1);
+    const bool last_wave = y1 >= yb1;
     const int col = map_index(x0 - H + lane, nx, FUSED ? kPeriodic : M.bc[0]);
     const bool store_lane = lane >= H && lane < 64 - H && (x0 - H + lane) < nx;
     const Fields<T, 2> U0 = fields<T, 2>(M.s[a.src]);
     double qmax = 0.0;
     bool bad = false;
-    if (y0 < ny && (active || last_stage)) {
-      const Fields<T, 2> Uout =
-          (FUSED || a.stage == 2) ? fields<T, 2>(M.s[1 - a.src]) : fields<T, 2>(M.w);
-      if (!active) {
+    const Fields<T, 2> Uout =
+        (FUSED || a.stage == 2) ? fields<T, 2>(M.s[1 - a.src]) : fields<T, 2>(M.w);
+    if (!active) {
+      if (last_stage) {
         for (int y = y0; y < y1; ++y) {
           const int gi = y * nx + col;
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (store_lane) Uout.f[q][gi] = U0.f[q][gi];
         }
-      } else {
-        StripMarch<T, FUSED> S;
-        S.U0 = U0;
-        S.Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
-        S.Uout = Uout;
-        S.g = gas_of<T>(M);
-        const double c1 = FUSED ? 0.5 * dt : (a.stage == 1 ? 0.5 * dt : dt);
-        S.kx1 = (T)(c1 * M.inv_dx[0]);
-        S.ky1 = (T)(c1 * M.inv_dx[1]);
-        S.kx2 = (T)(dt * M.inv_dx[0]);
-        S.ky2 = (T)(dt * M.inv_dx[1]);
-        S.inv_dx = M.inv_dx;
-        S.gamma = M.gamma;
-        S.nx = nx;
-        S.ny = ny;
-        S.col = (unsigned)col;
-        S.first = y0 - H;
-        S.bcy = FUSED ? kPeriodic : M.bc[1];
-        S.base_is_input = FUSED || a.stage == 1;
-        S.cfl = a.cfl != 0 && last_stage;
-        S.store_lane = store_lane;
-        S.qmax = 0.0;
-        S.bad = false;
-        S.run((y1 - y0) + 2 * H);
-        qmax = S.qmax;
-        bad = S.bad;
       }
+    } else if (y0 < y1) {
+      StripMarch<T, FUSED> S;
+      S.U0 = U0;
+      S.Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
+      S.Uout = Uout;
+      S.g = gas_of<T>(M);
+      const double c1 = FUSED ? 0.5 * dt : (a.stage == 1 ? 0.5 * dt : dt);
+      S.kx1 = (T)(c1 * M.inv_dx[0]);
+      S.ky1 = (T)(c1 * M.inv_dx[1]);
+      S.kx2 = (T)(dt * M.inv_dx[0]);
+      S.ky2 = (T)(dt * M.inv_dx[1]);
+      S.inv_dx[0] = M.inv_dx[0];
+      S.inv_dx[1] = M.inv_dx[1];
+      S.gamma = M.gamma;
+      S.nx = nx;
+      S.ny = ny;
+      S.col = (unsigned)col;
+      S.first = y0 - 2;
+      S.bcy = FUSED ? kPeriodic : M.bc[1];
+      S.base_is_input = FUSED || a.stage == 1;
+      S.cfl = a.cfl != 0 && last_stage;
+      S.store_lane = store_lane;
+      S.qmax = 0.0;
+      S.bad = false;
+      S.lane = lane;
+      // fused: a wave that is not the block's last reads the next wave's
+      // first four stage-1 rows; every wave but the first leaves its own
+      S.share_out = (share && wave > 0) ? lds_rows + wave * 1024 : nullptr;
+      S.share_in = (share && !last_wave) ? lds_rows + (wave + 1) * 1024 : nullptr;
+      const int npush = (y1 - y0) + (FUSED ? (S.share_in ? 4 : 8) : 4);
+      S.run(npush, share);
+      qmax = S.qmax;
+      bad = S.bad;
+    } else if (share) {
+      __syncthreads();  // an idle wave passes the block's one barrier too
     }
     if (a.cfl && active && last_stage) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);
   }

@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "euler_kernels.h"
+#include "euler_march2d.h"
 #include "euler_resident1d.h"
 #include "kernel_table.h"
 #include "paraiso.h"
@@ -360,7 +361,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   int et[3] = {v.tile[0], v.tile[1], v.tile[2]};
   if (v.lds == 2 && d == 2) {
     et[0] = 64 - 2 * (v.fuse ? 4 : 2);
-    et[1] = v.tile[1] * (threads / 64);
+    et[1] = v.fuse ? march2d_item_rows(threads / 64, v.tile[1]) : v.tile[1] * (threads / 64);
   } else if (v.lds == 2) {
     et[0] = 60;  // rows = waves, planes = tile[2]
   }
@@ -412,6 +413,11 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
     int64_t nmax = 1;
     for (const auto& m : c->meshes) nmax = std::max<int64_t>(nmax, m.n[0]);
     shmem = (size_t)c->esize * (6 * (size_t)nmax + 3);
+  }
+  G.rows = v.tile[1];
+  if (v.lds == 2 && d == 2 && v.fuse && march2d_shares(threads / 64, v.tile[1])) {
+    // each wave but the first leaves its first four stage-1 rows in LDS
+    shmem = (size_t)c->esize * 4 * 4 * 64 * (threads / 64);
   }
   if (v.lds == 2 && d == 3) {
     const int nw = v.tile[1];

@@ -2,7 +2,7 @@
 
     python -m paper_1204_4779_amd.tuner measure --workload box512 --db DB.jsonl
         benchmark every statically valid variant on the GPU (resumes a partial DB)
-    python -m paper_1204_4779_amd.tuner gain --db DB.jsonl [--seeds 9] [--frac 0.1]
+    python -m paper_1204_4779_amd.tuner gain --db DB.jsonl [--seeds 15] [--frac 0.1]
         replay the database: MLP-guided vs random vs PAGSA search at the same budget
 """
 from __future__ import annotations
@@ -39,7 +39,7 @@ def cmd_measure(a):
     bench.close()
 
 
-def gain_study(db: DB, ndim: int, esize: int, seeds: int = 9, frac: float = 0.1, log=log) -> dict:
+def gain_study(db: DB, ndim: int, esize: int, seeds: int = 15, frac: float = 0.1, log=log) -> dict:
     cands = search.candidates(ndim, esize)
     ev = search.ReplayEvaluator(db)
     truth = search.exhaustive(cands, ev)
@@ -87,7 +87,7 @@ def main(argv=None):
     g = sub.add_parser("gain")
     g.add_argument("--workload", default="box512", choices=sorted(measure.WORKLOADS))
     g.add_argument("--db", required=True)
-    g.add_argument("--seeds", type=int, default=9)
+    g.add_argument("--seeds", type=int, default=15)
     g.add_argument("--frac", type=float, default=0.1)
     g.add_argument("--out", default=None)
     a = ap.parse_args(argv)

@@ -9,8 +9,9 @@ cost in seconds) and stop once their benchmark budget is spent:
   pagsa        the paper's genetic simulated annealing: parents drawn from the
                database at a random temperature, children by mutation,
                crossover or triangulation with probability 1/3 each;
-  mlp          an MLP cost model, trained on the GPU on what has been
-               measured so far, proposes the next variants to benchmark.
+  mlp          an ensemble of MLP cost models, trained on the GPU on what has
+               been measured so far, proposes the next variants to benchmark
+               (each member picks one of a batch: Thompson-style sampling).
 """
 from __future__ import annotations
 
@@ -214,8 +215,16 @@ def pagsa(cands, evaluate, budget: float, rng, ndim: int, seed_variants) -> Trac
 
 # ---- MLP-guided --------------------------------------------------------------------------
 
-def mlp_guided(cands, evaluate, budget: float, rng, ndim: int, esize: int, init: int = 8, batch: int = 4,
-               epochs: int = 400, model_seed: int = 0) -> Trace:
+def mlp_guided(cands, evaluate, budget: float, rng, ndim: int, esize: int, init: int = 8, batch: int = 8,
+               epochs: int = 200, ensemble: int = 8, model_seed: int = 0) -> Trace:
+    """Model-guided search.  After `init` random variants, rounds of: fit an
+    ensemble of networks (different initial weights) to the standardised log
+    speed of everything measured, then benchmark `batch` unmeasured variants,
+    the b-th being the best predicted by member b mod `ensemble`.  The members
+    agree where the data pin the model down and disagree elsewhere, so the
+    batch mixes exploitation with exploration of regions still uncertain
+    (a cheap form of Thompson sampling); a single greedy model tends to
+    settle on the first good region it finds."""
     from .model import CostModel
     tr = Trace("mlp")
     F = np.array([sp.features(v, ndim, esize) for v in cands], dtype=np.float64)
@@ -230,7 +239,7 @@ def mlp_guided(cands, evaluate, budget: float, rng, ndim: int, esize: int, init:
         r = evaluate(cands[i])
         measured[int(i)] = r["mu"]
         tr.record(sp.key(cands[i]), r["mu"], r["cost"])
-    model = CostModel(F.shape[1], 64, seed=model_seed)
+    models = [CostModel(F.shape[1], 64, seed=model_seed * 16 + e) for e in range(ensemble)]
     while tr.spent < budget and len(measured) < len(cands):
         idx = np.array(sorted(measured))
         y = np.array([measured[i] for i in idx])
@@ -240,9 +249,16 @@ def mlp_guided(cands, evaluate, budget: float, rng, ndim: int, esize: int, init:
         else:
             ly = np.log(np.where(ok, y, y[ok].min() * 0.5))
             mu_y, sd_y = ly.mean(), ly.std() + 1e-9
-            model.fit(Fn[idx], (ly - mu_y) / sd_y, epochs=epochs)
-            pred = model.predict(Fn)
-            pick = [int(i) for i in np.argsort(-pred) if int(i) not in measured][:batch]
+            preds = []
+            for m in models:
+                m.fit(Fn[idx], (ly - mu_y) / sd_y, epochs=epochs)
+                preds.append(m.predict(Fn))
+            pick = []
+            for b in range(batch):
+                for i in np.argsort(-preds[b % ensemble]):
+                    if int(i) not in measured and int(i) not in pick:
+                        pick.append(int(i))
+                        break
         for i in pick:
             if tr.spent >= budget:
                 break

@@ -10,14 +10,12 @@ UNTUNED_2D = dict(tile=(64, 4), lds=0, fuse=0, waves_per_eu=0, threads=256)
 UNTUNED_3D = dict(tile=(16, 4, 4), lds=0, fuse=0, waves_per_eu=0, threads=256)
 
 TUNED = {
-    # register march, fused RK.  The rows per wave come from a sweep of rows
-    # 10..64 x threads x occupancy hint on top of the exhaustive search (whose
-    # tile axis has 8/16/32/64 only): the best counts put every strip of the
-    # mesh into one wave of resident blocks (FP32: 125 VGPRs, 4 waves per
-    # SIMD, 37 x 27 = 999 blocks of 4 waves; FP64: 2 waves per SIMD,
-    # 37 x 54 = 1998 blocks of 2 waves)
-    ("kh2048", "f32"): dict(tile=(64, 19), lds=2, fuse=1, waves_per_eu=0, threads=256),
-    ("kh2048", "f64"): dict(tile=(64, 38), lds=2, fuse=1, waves_per_eu=0, threads=128),
+    # register march, fused RK, stage-1 rows shared between the 4 waves of a
+    # block.  The rows per wave come from a sweep of rows x threads x
+    # occupancy hint on top of the exhaustive search (whose tile axis has
+    # 8/16/32/64 only); FP32 at <= 128 VGPRs (4 waves per SIMD), FP64 at 2.
+    ("kh2048", "f32"): dict(tile=(64, 16), lds=2, fuse=1, waves_per_eu=4, threads=256),
+    ("kh2048", "f64"): dict(tile=(64, 40), lds=2, fuse=1, waves_per_eu=0, threads=256),
     # 3D register march, one stage per launch: 60 columns x 4 rows per block,
     # 64-plane chunks, VGPRs capped at 168 (3 waves per SIMD)
     ("box256", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3),
