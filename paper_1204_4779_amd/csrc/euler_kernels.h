@@ -226,6 +226,23 @@ struct Fields {
   __attribute__((address_space(1))) T* f[D + 2];
 };
 
+// The same field pointers moved to scalar registers.  They are read from
+// the mesh table in global memory, which the compiler must load per lane
+// (the kernel writes global memory); every lane holds the same values, so
+// reading them from the first lane is exact, and scalar bases let each
+// access use the scalar-base form with a 32-bit lane offset.
+template <typename T, int D>
+__device__ __forceinline__ Fields<T, D> uniform(Fields<T, D> f) {
+#pragma unroll
+  for (int q = 0; q < D + 2; ++q) {
+    const unsigned long long v = (unsigned long long)f.f[q];
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    f.f[q] = (__attribute__((address_space(1))) T*)(((unsigned long long)hi << 32) | lo);
+  }
+  return f;
+}
+
 template <typename T, int D>
 __device__ __forceinline__ Fields<T, D> fields(void* const* p) {
   Fields<T, D> r;

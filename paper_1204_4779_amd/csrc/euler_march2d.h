@@ -352,9 +352,9 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
       }
     } else if (y0 < y1) {
       StripMarch<T, FUSED> S;
-      S.U0 = U0;
-      S.Uin = (FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w);
-      S.Uout = Uout;
+      S.U0 = uniform(U0);
+      S.Uin = uniform((FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w));
+      S.Uout = uniform(Uout);
       S.g = gas_of<T>(M);
       const double c1 = FUSED ? 0.5 * dt : (a.stage == 1 ? 0.5 * dt : dt);
       S.kx1 = (T)(c1 * M.inv_dx[0]);

@@ -83,27 +83,181 @@ __device__ __forceinline__ bool pipe_push5(RowPipe5<T>& P, const T* c, int n, co
   return done;
 }
 
+// One wave's z-march through one chunk of planes.  Pushes k = 0 .. npush-1
+// bring plane first + k; y-faces are formed for planes 2 <= k < npush - 2
+// (the assembled ones), and from k = 4 on each push assembles plane
+// first + k - 2.  The steady state (both) is unrolled six-fold, so the
+// register rings and the LDS slots (plane buffer k mod 2, y-flux ring k mod
+// 3) are compile-time in the unrolled body.
+template <typename T>
+struct PlaneMarch {
+  Fields<T, 3> U0, Uin, Uout;
+  Gas<T> g;
+  T kx, ky, kz;
+  double inv_dx[3];
+  double gamma;
+  int nz, plane, first, bcz;
+  unsigned own_bytes, halo_bytes;  // lane offsets of the own and halo rows within a plane
+  int wave, NW, NR, lane, hrel;
+  bool has_halo, store_lane, cfl;
+  T* sV;
+  T* sG;
+  int vslot, gslot;
+  RowPipe5<T> P;
+  T u_nx[5], uh_nx[5], base_nx[5];
+  double qmax;
+  bool bad;
+
+  __device__ __forceinline__ unsigned hide(unsigned b) const {
+    asm volatile("" : "+v"(b));
+    return b;
+  }
+  static __device__ __forceinline__ __attribute__((address_space(1))) T* at(
+      __attribute__((address_space(1))) T* row, unsigned bytes) {
+    return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)row + bytes);
+  }
+  __device__ __forceinline__ int zoff(int k) const { return map_index(first + k, nz, bcz) * plane; }
+
+  // loads of push k (own row, halo row if its y-faces are needed, base of
+  // the plane assembled at push k)
+  __device__ __forceinline__ void load(int k, bool yp, int npush) {
+    const int zo = zoff(k);
+    const unsigned ob = hide(own_bytes);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) u_nx[q] = *at(Uin.f[q] + zo, ob);
+    if (has_halo && yp) {
+      const unsigned hb = hide(halo_bytes);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) uh_nx[q] = *at(Uin.f[q] + zo, hb);
+    }
+    if (k >= 4) {
+      const int zb = (first + k - 2) * plane;  // assembled planes lie inside the mesh
+#pragma unroll
+      for (int q = 0; q < 5; ++q) base_nx[q] = *at(U0.f[q] + zb, ob);
+    }
+  }
+
+  // push k with V buffer VB = k mod 2 and y-flux slot GB = k mod 3 (compile
+  // time in the unrolled steady state, -1: from k); YF: form the y-faces;
+  // N: pipeline count (4: four or more)
+  template <int VB, int GB, int N, int YF>
+  __device__ __forceinline__ void push(int k, int npush) {
+    const int vb = VB >= 0 ? VB : (k & 1);
+    const int gb = GB >= 0 ? GB : (k % 3);
+    const bool yface = YF >= 0 ? (YF != 0) : (k >= 2 && k < npush - 2);
+    const int n = N >= 0 ? N : min(k, 4);
+    T u[5], uh[5], base[5], v[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      u[q] = u_nx[q];
+      uh[q] = uh_nx[q];
+      base[q] = base_nx[q];
+    }
+    if (k + 1 < npush) load(k + 1, k + 1 >= 2 && k + 1 < npush - 2, npush);
+    prim_of_cons<T, 3>(u, v, g);
+    T* Vs = sV + vb * vslot;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Vs[(q * NR + wave + 2) * 64 + lane] = v[q];
+    if (has_halo && yface) {
+      T vh[5];
+      prim_of_cons<T, 3>(uh, vh, g);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Vs[(q * NR + hrel) * 64 + lane] = vh[q];
+    }
+    __syncthreads();
+    if (yface) {
+      T vl[5], vr[5], G[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T* c = Vs + (q * NR + wave) * 64 + lane;
+        face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+      }
+      hllc<T, 3, 1>(vl, vr, G, g);
+      T* Gs = sG + gb * gslot;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + wave) * 64 + lane] = G[q];
+      if (wave == NW - 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T* c = Vs + (q * NR + wave + 1) * 64 + lane;
+          face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+        }
+        hllc<T, 3, 1>(vl, vr, G, g);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + NW) * 64 + lane] = G[q];
+      }
+    }
+    T accz[5], va[5];
+    if (pipe_push5<T>(P, v, n, g, accz, va)) {
+      const int zo = first + k - 2;
+      T dF[5];
+      xflux_diff3<T>(va, g, dF);
+      const int rb = gb == 0 ? 1 : (gb == 1 ? 2 : 0);  // slot of plane k - 2: (k + 1) mod 3
+      const T* Gs = sG + rb * gslot;
+      T out[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T dy = Gs[(q * (NW + 1) + wave) * 64 + lane] - Gs[(q * (NW + 1) + wave + 1) * 64 + lane];
+        T acc = kx * dF[q];
+        acc += ky * dy;
+        acc += kz * accz[q];
+        out[q] = base[q] + acc;
+      }
+      if (store_lane) {
+        const unsigned ob = hide(own_bytes);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) *at(Uout.f[q] + zo * plane, ob) = out[q];
+        if (cfl) {
+          const double qv = cfl_q<T, 3>(out, inv_dx, gamma);
+          bad |= !(qv > 0.0);
+          qmax = qv > qmax ? qv : qmax;
+        }
+      }
+    }
+  }
+
+  __device__ __forceinline__ void run(int npush) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) uh_nx[q] = base_nx[q] = T(0);
+    load(0, false, npush);
+    int k = 0;
+    // warm-up and short chunks: run-time phase
+#pragma clang loop unroll(disable)
+    for (; k < 4 && k < npush; ++k) push<-1, -1, -1, -1>(k, npush);
+    // steady state: y-faces and output, k = 4 .. npush - 3, six-fold
+    for (; k + 6 <= npush - 2; k += 6) {
+      push<0, 1, 4, 1>(k, npush);
+      push<1, 2, 4, 1>(k + 1, npush);
+      push<0, 0, 4, 1>(k + 2, npush);
+      push<1, 1, 4, 1>(k + 3, npush);
+      push<0, 2, 4, 1>(k + 4, npush);
+      push<1, 0, 4, 1>(k + 5, npush);
+    }
+#pragma clang loop unroll(disable)
+    for (; k < npush; ++k) push<-1, -1, 4, -1>(k, npush);
+  }
+};
+
 template <typename T, int W>
 __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, LdsGeom) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
   __shared__ int s_item;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int NW = blockDim.x >> 6;
   const int NR = NW + 4;            // rows in an LDS plane
   T* sV = reinterpret_cast<T*>(smem);            // [2][5][NR][64]
   T* sG = sV + 2 * 5 * NR * 64;                  // [3][5][NW+1][64]
-  const int vslot = 5 * NR * 64, gslot = 5 * (NW + 1) * 64;
   ItemLoop it{0, 1};
   for (int item; (item = next_item(a, it, &s_item, a.stage - 1)) >= 0;) {
+    item = __builtin_amdgcn_readfirstlane(item);
     const Tile t = tile_of(a, item);
     const MeshDev& M = a.meshes[t.m];
     bool active;
     const double dt = step_dt(a, t.m, active);
     const bool last_stage = a.stage == 2;
     if (last_stage && t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
-    const Gas<T> g = gas_of<T>(M);
     const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
     const int x0 = t.org[0], y0 = t.org[1], z0 = t.org[2];
     const int z1 = min(z0 + a.tile[2], nz);
@@ -116,7 +270,6 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
     const int yhalo = map_index(y0 - 2 + hrel, ny, M.bc[1]);
     const bool store_lane = lane >= 2 && lane < 62 && (x0 - 2 + lane) < nx && yrow < ny;
     const Fields<T, 3> U0 = fields<T, 3>(M.s[a.src]);
-    const Fields<T, 3> Uin = a.stage == 1 ? U0 : fields<T, 3>(M.w);
     const Fields<T, 3> Uout = a.stage == 2 ? fields<T, 3>(M.s[1 - a.src]) : fields<T, 3>(M.w);
     const int plane = nx * ny;
     double qmax = 0.0;
@@ -131,107 +284,40 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
         }
     } else {
       const double cdt = (a.stage == 1 ? 0.5 : 1.0) * dt;
-      const T kx = (T)(cdt * M.inv_dx[0]), ky = (T)(cdt * M.inv_dx[1]), kz = (T)(cdt * M.inv_dx[2]);
-      RowPipe5<T> P;
-      const int first = z0 - 2;
-      const int npush = (z1 - z0) + 4;
-      const int own_off = yown * nx + col, halo_off = yhalo * nx + col;
-      // loads run one plane ahead of their use (own row, halo row, base state)
-      T u_nx[5], uh_nx[5], base_nx[5];
+      PlaneMarch<T> S;
+      S.U0 = uniform(U0);
+      S.Uin = uniform(a.stage == 1 ? U0 : fields<T, 3>(M.w));
+      S.Uout = uniform(Uout);
+      S.g = gas_of<T>(M);
+      S.kx = (T)(cdt * M.inv_dx[0]);
+      S.ky = (T)(cdt * M.inv_dx[1]);
+      S.kz = (T)(cdt * M.inv_dx[2]);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) uh_nx[q] = base_nx[q] = T(0);
-      {
-        const int zk = map_index(first, nz, M.bc[2]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) u_nx[q] = Uin.f[q][zk * plane + own_off];
-      }
-      for (int k = 0; k < npush; ++k) {
-        // only planes that are assembled need their y-faces (not the 2 + 2 halo planes)
-        const bool yplane = k >= 2 && k < npush - 2;
-        T u[5], uh[5], base[5], v[5];
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-          u[q] = u_nx[q];
-          uh[q] = uh_nx[q];
-          base[q] = base_nx[q];
-        }
-        if (k + 1 < npush) {
-          const int zn = map_index(first + k + 1, nz, M.bc[2]);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) u_nx[q] = Uin.f[q][zn * plane + own_off];
-          if (has_halo && k + 1 >= 2 && k + 1 < npush - 2) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) uh_nx[q] = Uin.f[q][zn * plane + halo_off];
-          }
-          if (k + 1 >= 4) {  // base of the plane assembled at push k + 1
-            const int zb = first + k + 1 - 2;
-#pragma unroll
-            for (int q = 0; q < 5; ++q) base_nx[q] = U0.f[q][zb * plane + own_off];
-          }
-        }
-        prim_of_cons<T, 3>(u, v, g);
-        T* Vs = sV + (k & 1) * vslot;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) Vs[(q * NR + wave + 2) * 64 + lane] = v[q];
-        if (has_halo && yplane) {
-          T vh[5];
-          prim_of_cons<T, 3>(uh, vh, g);
-#pragma unroll
-          for (int q = 0; q < 5; ++q) Vs[(q * NR + hrel) * 64 + lane] = vh[q];
-        }
-        __syncthreads();
-        // y-face below this row (LDS rows wave .. wave+3), and above for the last wave
-        if (yplane) {
-          T vl[5], vr[5], G[5];
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            const T* c = Vs + (q * NR + wave) * 64 + lane;
-            face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
-          }
-          hllc<T, 3, 1>(vl, vr, G, g);
-          T* Gs = sG + (k % 3) * gslot;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + wave) * 64 + lane] = G[q];
-          if (wave == NW - 1) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) {
-              const T* c = Vs + (q * NR + wave + 1) * 64 + lane;
-              face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
-            }
-            hllc<T, 3, 1>(vl, vr, G, g);
-#pragma unroll
-            for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + NW) * 64 + lane] = G[q];
-          }
-        }
-        // z pipeline of this column; assembles plane first + k - 2
-        T accz[5];
-        T va[5];
-        if (pipe_push5<T>(P, v, k, g, accz, va)) {
-          const int zo = first + k - 2;
-          T dF[5];
-          xflux_diff3<T>(va, g, dF);
-          const T* Gs = sG + ((k + 1) % 3) * gslot;  // slot of plane k - 2
-          T out[5];
-          const int gi = zo * plane + own_off;
-#pragma unroll
-          for (int q = 0; q < 5; ++q) {
-            const T dy = Gs[(q * (NW + 1) + wave) * 64 + lane] - Gs[(q * (NW + 1) + wave + 1) * 64 + lane];
-            T acc = kx * dF[q];
-            acc += ky * dy;
-            acc += kz * accz[q];
-            out[q] = base[q] + acc;
-          }
-          if (store_lane) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) Uout.f[q][gi] = out[q];
-            if (last_stage && a.cfl) {
-              const double qv = cfl_q<T, 3>(out, M.inv_dx, M.gamma);
-              bad |= !(qv > 0.0);
-              qmax = fmax(qmax, qv);
-            }
-          }
-        }
-      }
+      for (int x = 0; x < 3; ++x) S.inv_dx[x] = M.inv_dx[x];
+      S.gamma = M.gamma;
+      S.nz = nz;
+      S.plane = plane;
+      S.first = z0 - 2;
+      S.bcz = M.bc[2];
+      S.own_bytes = (unsigned)(yown * nx + col) * (unsigned)sizeof(T);
+      S.halo_bytes = (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T);
+      S.wave = wave;
+      S.NW = NW;
+      S.NR = NR;
+      S.lane = lane;
+      S.hrel = hrel;
+      S.has_halo = has_halo;
+      S.store_lane = store_lane;
+      S.cfl = last_stage && a.cfl;
+      S.sV = sV;
+      S.sG = sG;
+      S.vslot = 5 * NR * 64;
+      S.gslot = 5 * (NW + 1) * 64;
+      S.qmax = 0.0;
+      S.bad = false;
+      S.run((z1 - z0) + 4);
+      qmax = S.qmax;
+      bad = S.bad;
       __syncthreads();  // LDS reuse by the next item
     }
     if (a.cfl && active && last_stage) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);
