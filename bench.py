@@ -44,13 +44,20 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes, each scaled by the reading of a plain 512 MiB device copy
 # (factors 2.000 and 1.000); valid only for the kernel sources they were taken
 # on (hash of the device headers) and the variant named.
-TRAFFIC = {"sources": "9ce98fc80e2db3c8", "variant": {"tile": [64, 16], "lds": 2, "fuse": 1},
-           "bytes_per_launch": 167.0e6}
+TRAFFIC = {"sources": "c3b27d378723d495",
+           "variant": {"tile": [64, 16], "lds": 2, "fuse": 1, "waves_per_eu": 4, "threads": 256},
+           "bytes_per_launch": 161.3e6}
 
 
-KERNEL_NAME = {(2, 1): "k_march2d<float,0,true>", (2, 0): "k_march2d<float,0,false>",
-               (1, 1): "k_fused_lds<float,2>", (1, 0): "k_stage_lds<float,2>",
-               (0, 0): "k_stage_direct<float,2>", (0, 1): "k_fused_direct<float,2>"}
+def kernel_name(v: dict) -> str:
+    """The dominant kernel of a 2D FP32 variant (one launch per fused step)."""
+    w = v.get("waves_per_eu", 0)
+    fused = "true" if v.get("fuse", 1) else "false"
+    lds = v.get("lds", 1)
+    if lds == 2:
+        return f"k_march2d<float,{w},{fused}>"
+    fam = {1: "fused_lds" if v.get("fuse", 1) else "stage_lds", 0: "fused_direct" if v.get("fuse", 1) else "stage_direct"}
+    return f"k_{fam[lds]}<float,2,{w}>"
 
 
 def _kernel_source_hash() -> str:
@@ -268,7 +275,7 @@ def main():
         traffic = TRAFFIC["bytes_per_launch"]
     roofline = {"bound": "alu", "achieved": round(achieved_tf, 3), "peak": ALU_PEAK_TFLOPS["f32"],
                 "unit": "TFLOP/s", "frac": round(achieved_tf / ALU_PEAK_TFLOPS["f32"], 4), "traffic": traffic,
-                "kernel": KERNEL_NAME.get((tuned32.get("lds", 1), tuned32.get("fuse", 1)), "?"), "flops_per_launch": flops, "launch_ms": round(launch_ms, 5),
+                "kernel": kernel_name(tuned32), "flops_per_launch": flops, "launch_ms": round(launch_ms, 5),
                 "peak_packed_f32": ALU_PEAK_PACKED_F32}
     hbm = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": bytes_launch}
