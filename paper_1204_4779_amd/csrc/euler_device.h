@@ -217,14 +217,16 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
   const T rstar = ak * inv;
   const T estar = inv * ((sk - uk) * ek + (sstar - uk) * (ak * sstar + pk));
 
-  // F_K + w (U*_K - U_K)
-  f[0] = uk * rk + w * (rstar - rk);
+  // F_K + w (U*_K - U_K).  Every transverse component is v_t times the mass
+  // component: rho u v_t + w (chi v_t - rho v_t) = v_t (rho u + w (chi - rho)).
+  const T mk = rk * uk;
+  f[0] = mk + w * (rstar - rk);
 #pragma unroll
   for (int b = 0; b < D; ++b) {
-    const T mk = rk * vk[1 + b];
-    const T fk = uk * mk + (b == AX ? pk : T(0));
-    const T mstar = rstar * (b == AX ? sstar : vk[1 + b]);
-    f[1 + b] = fk + w * (mstar - mk);
+    if (b == AX)
+      f[1 + b] = mk * uk + pk + w * (rstar * sstar - mk);
+    else
+      f[1 + b] = vk[1 + b] * f[0];
   }
   f[D + 1] = uk * (ek + pk) + w * (estar - ek);
 }

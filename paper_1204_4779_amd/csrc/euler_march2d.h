@@ -86,10 +86,10 @@ struct RowPipe {
 // Push V(row k) as `c` into a stage pipeline that has received N rows
 // before this one (N = 4 stands for 4 or more: the steady state; N = -1
 // takes the count from n at run time).  When the count is 4 or more the
-// update acc = kx dFx + ky dGy of row k-2 is written to acc.
+// updated row k-2, base + kx dFx + ky dGy, is written to out.
 template <typename T, int N>
-__device__ __forceinline__ void pipe_push(RowPipe<T>& P, const T* c, const Gas<T>& g, T kx, T ky, T* acc,
-                                          int n = N) {
+__device__ __forceinline__ void pipe_push(RowPipe<T>& P, const T* c, const Gas<T>& g, T kx, T ky, const T* base,
+                                          T* out, int n = N) {
   if (N >= 2 || (N < 0 && n >= 2)) {
     T lo_b[4], up_b[4];
 #pragma unroll
@@ -105,10 +105,7 @@ __device__ __forceinline__ void pipe_push(RowPipe<T>& P, const T* c, const Gas<T
         T dF[4];
         xflux_diff<T>(P.a, g, dF);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          acc[q] = kx * dF[q];
-          acc[q] += ky * (P.g[q] - G[q]);
-        }
+        for (int q = 0; q < 4; ++q) out[q] = fma(ky, P.g[q] - G[q], fma(kx, dF[q], base[q]));
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) P.g[q] = G[q];
@@ -215,13 +212,10 @@ struct StripMarch {
     for (int q = 0; q < 4; ++q) ub[4][q] = base[q];
     T v[4];
     prim_of_cons<T, 2>(u, v, g);
-    T acc[4];
-    pipe_push<T, S1>(P1, v, g, kx1, ky1, acc);
+    // stage-1 output: row first + k - 2, base ub[2]
+    T u1[4];
+    pipe_push<T, S1>(P1, v, g, kx1, ky1, ub[2], u1);
     if constexpr (S1 >= 4) {
-      // stage-1 output: row first + k - 2, base ub[2]
-      T u1[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) u1[q] = ub[2][q] + acc[q];
       if constexpr (!FUSED) {
         emit(first + k - 2, u1);
       } else {
@@ -231,15 +225,10 @@ struct StripMarch {
 #pragma unroll
           for (int q = 0; q < 4; ++q) v1_out[q * 64 + lane] = v1[q];
         }
-        T acc2[4];
-        pipe_push<T, S2>(P2, v1, g, kx2, ky2, acc2, n2);
-        if constexpr (S2 >= 4) {
-          // stage-2 output: row first + k - 4, base ub[0]
-          T u2[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) u2[q] = ub[0][q] + acc2[q];
-          emit(first + k - 4, u2);
-        }
+        // stage-2 output: row first + k - 4, base ub[0]
+        T u2[4];
+        pipe_push<T, S2>(P2, v1, g, kx2, ky2, ub[0], u2, n2);
+        if constexpr (S2 >= 4) emit(first + k - 4, u2);
       }
     }
   }
@@ -253,11 +242,8 @@ struct StripMarch {
     T v1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) v1[q] = row[q * 64 + lane];
-    T acc2[4];
-    pipe_push<T, 4>(P2, v1, g, kx2, ky2, acc2);
     T u2[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) u2[q] = ub[0][q] + acc2[q];
+    pipe_push<T, 4>(P2, v1, g, kx2, ky2, ub[0], u2);
     emit(first + k - 4, u2);
   }
 

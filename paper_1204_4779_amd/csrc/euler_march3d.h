@@ -198,10 +198,7 @@ struct PlaneMarch {
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
         const T dy = Gs[(q * (NW + 1) + wave) * 64 + lane] - Gs[(q * (NW + 1) + wave + 1) * 64 + lane];
-        T acc = kx * dF[q];
-        acc += ky * dy;
-        acc += kz * accz[q];
-        out[q] = base[q] + acc;
+        out[q] = fma(kz, accz[q], fma(ky, dy, fma(kx, dF[q], base[q])));
       }
       if (store_lane) {
         const unsigned ob = hide(own_bytes);
