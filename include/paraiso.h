@@ -89,10 +89,13 @@ typedef struct paraiso_mesh {
  *                1: LDS tiles, each face flux computed once per tile;
  *                2: register march (2D and 3D): a wave per strip of 64
  *                   columns (tile[0] = 64) marching along the last axis,
- *                   x-neighbours by lane shifts; 2D: tile[1] rows per wave;
- *                   3D: tile[1] = 4 or 8 rows (= waves) per block, tile[2]
- *                   planes per block, one stage per launch (fuse = 0); the
- *                   fused 2D form needs periodic boundaries;
+ *                   x-neighbours by lane shifts; 2D: tile[1] rows per wave,
+ *                   threads / 64 waves per block; the fused 2D form needs
+ *                   periodic boundaries, and with at least 2 waves of at
+ *                   least 6 rows its waves share stage-1 rows through LDS
+ *                   (a block then covers waves * rows - 2 rows); 3D:
+ *                   tile[1] = 4 or 8 rows (= waves) per block, tile[2]
+ *                   planes per block, one stage per launch (fuse = 0);
  *                3: resident (1D, at most 4096 cells per mesh in FP32 and
  *                   3407 in FP64, the LDS of one workgroup holding
  *                   8 * (6n + 3) bytes): one workgroup per mesh runs a

@@ -147,3 +147,40 @@ def test_static_validity_examples():
     ok = sp.make_variant((16, 8, 8), 1, 0, 0, 3)
     assert sp.statically_valid(ok, 3, 4)
     assert sp.statically_valid(sp.make_variant((64, 64, 64), 0, 1, 5, 3), 3, 4)
+
+
+class _NumpyCostModel:
+    """The cost model with the oracle's FP64 MLP in place of the GPU kernels."""
+
+    def __init__(self, in_dim, hidden=64, seed=0, lr=3e-3):
+        from oracle import mlp as om
+        self.om, self.in_dim, self.hidden, self.lr = om, in_dim, hidden, lr
+        rng = np.random.default_rng(seed)
+        self.p = rng.normal(scale=0.3, size=om.n_params(in_dim, hidden))
+        self.m = np.zeros_like(self.p)
+        self.v = np.zeros_like(self.p)
+        self.t = 0
+
+    def fit(self, X, y, epochs=200):
+        for _ in range(epochs):
+            _, g = self.om.loss_grad(X, y, self.p, self.in_dim, self.hidden)
+            self.t += 1
+            self.p, self.m, self.v = self.om.adam(self.p, g, self.m, self.v, self.lr, 0.9, 0.999, 1e-8, self.t)
+
+    def predict(self, X):
+        return self.om.forward(X, self.p, self.in_dim, self.hidden)[0]
+
+
+def test_mlp_guided_ensemble_loop(monkeypatch):
+    from paper_1204_4779_amd.tuner import model
+    monkeypatch.setattr(model, "CostModel", _NumpyCostModel)
+    db = _synthetic_db()
+    cands = search.candidates(3, 4)
+    ev = search.ReplayEvaluator(db)
+    truth = search.exhaustive(cands, ev)
+    budget = 0.1 * truth.spent
+    tr = search.mlp_guided(cands, ev, budget, np.random.default_rng(4), 3, 4, epochs=60, ensemble=4, batch=4)
+    keys = [k for k, _, _ in tr.evaluated]
+    assert len(keys) == len(set(keys))                   # nothing benchmarked twice
+    assert tr.spent - tr.evaluated[-1][2] < budget       # stops once the budget is spent
+    assert tr.best_mu >= 0.9 * truth.best_mu             # the smooth synthetic optimum is found
