@@ -149,7 +149,10 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
 int32_t paraiso_set_variant(paraiso_ctx* ctx, const paraiso_variant* v);
 int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
 
-/* The default variant the library picks for these meshes. */
+/* The default variant the library picks for these meshes (and applies in
+ * paraiso_init): 1D the resident kernel when every mesh fits one
+ * workgroup, else LDS tiles; 2D the fused register march when every mesh is
+ * periodic on both axes, else LDS tiles; 3D the register march. */
 int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
 
 /*

@@ -492,7 +492,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   return PARAISO_OK;
 }
 
-void default_variant(int ndim, int dtype, paraiso_variant* v) {
+// The LDS-tile variant: every dimension, boundary and size.
+void lds_variant(int ndim, paraiso_variant* v) {
   std::memset(v, 0, sizeof(*v));
   v->tile[0] = v->tile[1] = v->tile[2] = 1;
   v->lds = 1;
@@ -510,7 +511,49 @@ void default_variant(int ndim, int dtype, paraiso_variant* v) {
     v->tile[2] = 4;
     v->fuse = 0;
   }
-  (void)dtype;
+}
+
+// The default: the fastest family measured on an MI355X for the case.
+//   1D: the resident kernel when every mesh fits one workgroup's LDS
+//       (160 KiB on gfx950), else LDS tiles;
+//   2D: the fused register march when every mesh is periodic on both axes
+//       (FP32 20 rows x 4 waves, FP64 40 rows x 2 waves), else LDS tiles;
+//   3D: the register march, 4 rows x 64-plane chunks, at most 168 VGPRs.
+// Batches pull tiles from the persistent queue.
+void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) {
+  const int d = meshes[0].ndim;
+  const bool f64 = meshes[0].dtype == PARAISO_F64;
+  lds_variant(d, v);
+  if (d == 1) {
+    int64_t nmax = 1;
+    for (int m = 0; m < count; ++m) nmax = std::max<int64_t>(nmax, meshes[m].n[0]);
+    const size_t esize = f64 ? 8 : 4;
+    if (nmax <= kResidentCells && esize * (6 * (size_t)nmax + 3) + 256 <= 163840) {
+      v->lds = 3;
+      v->fuse = 1;
+      v->tile[0] = (int32_t)nmax;
+    }
+  } else if (d == 2) {
+    bool periodic = true;
+    for (int m = 0; m < count; ++m)
+      periodic = periodic && meshes[m].bc[0] == PARAISO_PERIODIC && meshes[m].bc[1] == PARAISO_PERIODIC;
+    if (periodic) {
+      v->tile[0] = 64;
+      v->tile[1] = f64 ? 40 : 20;
+      v->lds = 2;
+      v->fuse = 1;
+      v->threads = f64 ? 128 : 256;
+    }
+  } else {
+    v->tile[0] = 64;
+    v->tile[1] = 4;
+    v->tile[2] = 64;
+    v->lds = 2;
+    v->fuse = 0;
+    v->waves_per_eu = 3;
+    v->threads = 256;
+  }
+  if (count > 1) v->persistent = 1;
 }
 
 }  // namespace
@@ -533,8 +576,7 @@ int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, parai
   if (!v) return fail(PARAISO_ERR_INVALID_ARG, "null variant pointer");
   int rc = validate_meshes(meshes, count);
   if (rc) return rc;
-  default_variant(meshes[0].ndim, meshes[0].dtype, v);
-  if (count > 1) v->persistent = 1;
+  default_variant(meshes, count, v);
   return PARAISO_OK;
 }
 
@@ -610,9 +652,14 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
     chunk += M.nchunks;
   }
   paraiso_variant v;
-  default_variant(c->ndim, c->dtype, &v);
-  if (count > 1) v.persistent = 1;
+  default_variant(meshes, count, &v);
   rc = apply_variant(c, v);
+  if (rc == PARAISO_ERR_UNSUPPORTED) {
+    // a device with less LDS than gfx950: the LDS-tile family always applies
+    lds_variant(c->ndim, &v);
+    if (count > 1) v.persistent = 1;
+    rc = apply_variant(c, v);
+  }
   if (rc) return bail(rc);
   rc = ctl_init(c, nullptr);
   if (rc) return bail(rc);

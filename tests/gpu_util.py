@@ -10,11 +10,13 @@ from paper_1204_4779_amd import binding as pb
 TOL = {"f64": 1e-12, "f32": 1e-5}
 
 VARIANTS = {
-    # name: (lds, fuse)
+    # name: (lds, fuse); "default": the library's own choice for the meshes
+    # (resident 1D, register march 2D periodic / 3D, else LDS tiles)
     "direct": dict(lds=0, fuse=0),
     "direct_fused": dict(lds=0, fuse=1),
     "lds": dict(lds=1, fuse=0),
     "lds_fused": dict(lds=1, fuse=1),
+    "default": None,
 }
 
 

@@ -105,10 +105,23 @@ def test_init_argument_errors_before_device_work(lib):
 
 
 def test_default_variant(lib):
+    # 2D periodic: the fused register march; any outflow axis: LDS tiles
     v = pb.paraiso_default_variant([_mesh()])
-    assert v.lds in (0, 1) and v.fuse in (0, 1) and v.tile[2] == 1
+    assert (v.lds, v.fuse, tuple(v.tile)) == (2, 1, (64, 20, 1)) and v.threads == 256
+    v = pb.paraiso_default_variant([_mesh(dtype=pb.F64)])
+    assert (v.lds, tuple(v.tile), v.threads) == (2, (64, 40, 1), 128)
+    v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, 1, 0))])
+    assert v.lds == 1 and v.fuse == 1 and v.persistent == 1
+    # 3D: the one-stage register march
     v3 = pb.paraiso_default_variant([_mesh(3, (4, 4, 4))])
-    assert all(t >= 1 for t in v3.tile)
+    assert (v3.lds, v3.fuse, tuple(v3.tile), v3.waves_per_eu) == (2, 0, (64, 4, 64), 3)
+    # 1D: resident while every mesh fits one workgroup's LDS
+    assert pb.paraiso_default_variant([_mesh(1, (4096, 1, 1))]).lds == 3
+    assert pb.paraiso_default_variant([_mesh(1, (4097, 1, 1))]).lds == 1
+    assert pb.paraiso_default_variant([_mesh(1, (3407, 1, 1), pb.F64)]).lds == 3
+    assert pb.paraiso_default_variant([_mesh(1, (3408, 1, 1), pb.F64)]).lds == 1
+    v1 = pb.paraiso_default_variant([_mesh(1, (100, 1, 1)), _mesh(1, (1000, 1, 1))])
+    assert (v1.lds, v1.tile[0], v1.persistent) == (3, 1000, 1)
 
 
 def test_version(lib):

@@ -21,6 +21,8 @@ SHAPES = {1: (203,), 2: (37, 21), 3: (19, 11, 10)}
 
 
 def _variant(name, ndim, tile=None):
+    if VARIANTS[name] is None:
+        return None
     v = dict(VARIANTS[name])
     v["tile"] = tile or default_tile(ndim)
     return v
@@ -176,12 +178,14 @@ def test_advance_matches_oracle_steps_2d():
 
 
 @pytest.mark.parametrize("persistent", [0, 1])
-def test_batch_members_equal_solo_runs(persistent):
-    sizes = [(20, 17), (64, 64), (9, 31), (50, 8)]
+@pytest.mark.parametrize("family", ["lds_fused", "march_shared"])
+def test_batch_members_equal_solo_runs(persistent, family):
+    sizes = [(20, 17), (64, 64), (9, 31), (130, 70)]
     probs = [inputs.random_state(2, n, seed=60 + k) for k, n in enumerate(sizes)]
     specs = [spec_of(p) for p in probs]
     dts = [oracle.cfl_dt(oracle_mesh(p), as_input(p.U, "f32"), 0.5) for p in probs]
-    v = dict(tile=(16, 8), lds=1, fuse=1, persistent=persistent)
+    v = {"lds_fused": dict(tile=(16, 8), lds=1, fuse=1, persistent=persistent),
+         "march_shared": dict(tile=(64, 8), lds=2, fuse=1, threads=256, persistent=persistent)}[family]
     b = gpu_solver(specs, "f32", v, [p.U for p in probs])
     b.step(dts)
     for k, p in enumerate(probs):
