@@ -1,0 +1,43 @@
+"""bench.py's contract pieces that need no GPU: the single-GPU guard, the
+roofline bookkeeping and the counted work per cell-update."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
+
+
+def test_algorithmic_bytes_and_flops():
+    assert bench.bytes_per_cell_update(2, 4) == 32
+    assert bench.bytes_per_cell_update(3, 8) == 80
+    # the ALU roof: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+    assert abs(bench.ALU_PEAK_TFLOPS["f32"] - 256 * 4 * 16 * 2 * 2.4e9 / 1e12) < 0.1
+
+
+def test_flop_count_matches_the_oracle_counter():
+    # the per-cell figure bench.py uses is what the counting build of the
+    # oracle reports for one step (+ CFL) of the KH workload
+    import oracle
+    from paper_1204_4779_amd import inputs
+    pr = inputs.kelvin_helmholtz_2d(256)
+    counts = oracle.count_ops(oracle.Mesh(2, pr.n, pr.gamma, pr.bc), pr.U, 1e-4)
+    per_cell = counts["add"] + counts["mul"] + counts["div"] + counts["sqrt"]
+    assert abs(per_cell - bench.FLOPS_PER_CELL_UPDATE[2]) / bench.FLOPS_PER_CELL_UPDATE[2] < 2e-3
+
+
+def test_kernel_name_follows_the_variant():
+    assert bench.kernel_name(dict(tile=(64, 20), lds=2, fuse=1, waves_per_eu=0)) == "k_march2d<float,0,true>"
+    assert bench.kernel_name(dict(tile=(64, 16), lds=2, fuse=0, waves_per_eu=4)) == "k_march2d<float,4,false>"
+    assert bench.kernel_name(dict(tile=(32, 16), lds=1, fuse=1)) == "k_fused_lds<float,2,0>"
