@@ -1,4 +1,5 @@
-// Register-march kernels for 2D periodic meshes (gfx950, wave64).
+// Register-march kernels for 2D meshes (gfx950, wave64): the fused step on
+// periodic meshes, one stage on periodic or outflow meshes.
 //
 // Each wave owns a strip of 64 columns: 64 - 2H interior columns plus H halo
 // columns per side (H = 4 for the fused step, 2 for one stage) and marches
@@ -26,10 +27,10 @@ namespace paraiso {
 // shifted down by two rows: rows [y0 + 2, y1 + 2) of its range [y0, y1).
 // The four stage-1 rows below its range are the first four stage-1 rows of
 // wave w + 1, which that wave leaves in LDS; only the last wave of a block
-// computes them itself.  Two rows of stage-1 recomputation per wave instead
-// of four per side, one barrier per work item, and the last wave, which has
-// the extra work, takes two rows fewer.  With one wave per block, or fewer
-// than 6 rows per wave, every wave works as a last wave.
+// computes them itself.  So stage 1 is recomputed for four rows per block
+// instead of eight per wave, at the cost of one barrier per work item; the
+// last wave, which has the extra work, takes two rows fewer.  With one wave
+// per block, or fewer than 6 rows per wave, every wave works as a last wave.
 __host__ __device__ constexpr bool march2d_shares(int nwaves, int rows) { return nwaves > 1 && rows >= 6; }
 // Rows of one work item of the fused march.
 __host__ __device__ constexpr int march2d_item_rows(int nwaves, int rows) {
