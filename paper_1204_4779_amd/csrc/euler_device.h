@@ -206,14 +206,15 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
   for (int b = 0; b < D; ++b) v2 += vk[1 + b] * vk[1 + b];
   const T ek = pk * g.inv_gm1 + T(0.5) * rk * v2;
 
-  // one reciprocal gives both S* = num/den and 1/(S_K - S*) = den/(S_K den - num)
-  const T e = sk * den - num;
-  const T r = Fp<T>::rcp(den * e);
-  // weight of the star correction: zero on supersonic faces
+  // one reciprocal gives both S* = num/den and 1/(S_K - S*) = den/(S_K den - num).
+  // The weight of the star correction is zero on supersonic faces; e = 1
+  // there keeps the (unused) star terms finite, so 0 * (U*_K - U_K) is 0.
   const bool sup = left_sup || right_sup;
+  const T e = sup ? T(1) : sk * den - num;
+  const T r = Fp<T>::rcp(den * e);
   const T w = sup ? T(0) : sk;
-  const T sstar = sup ? T(0) : num * e * r;
-  const T inv = sup ? T(0) : den * den * r;
+  const T sstar = num * e * r;
+  const T inv = den * den * r;
   const T rstar = ak * inv;
   const T estar = inv * ((sk - uk) * ek + (sstar - uk) * (ak * sstar + pk));
 
