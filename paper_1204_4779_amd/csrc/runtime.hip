@@ -297,6 +297,18 @@ int launch_cfl(paraiso_ctx* c) {
   return PARAISO_OK;
 }
 
+// The march kernels address a lane's cell with a 32-bit byte offset from a
+// scalar base: within a row in 2D, within a plane in 3D.
+bool march_offsets_fit(const paraiso_mesh* meshes, int count) {
+  for (int m = 0; m < count; ++m) {
+    const paraiso_mesh& p = meshes[m];
+    const int64_t span = p.ndim == 2 ? p.n[0] : p.n[0] * p.n[1];
+    const int64_t esize = p.dtype == PARAISO_F64 ? 8 : 4;
+    if (span * esize >= (int64_t(1) << 32)) return false;
+  }
+  return true;
+}
+
 int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string& why) {
   const int d = c->ndim;
   for (int a = 0; a < 3; ++a) {
@@ -323,6 +335,8 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   if (v.lds == 2) {
     if (d == 1) return why = "register march (lds = 2) exists for 2D and 3D meshes", PARAISO_ERR_UNSUPPORTED;
     if (v.tile[0] != 64) return why = "register march: tile[0] must be 64 (one wave of columns)", PARAISO_ERR_UNSUPPORTED;
+    if (!march_offsets_fit(c->meshes.data(), c->count))
+      return why = "register march: a row (2D) or plane (3D) spans 4 GiB or more", PARAISO_ERR_UNSUPPORTED;
     if (d == 2) {
       if (v.fuse)
         for (const auto& m : c->meshes)
@@ -533,6 +547,8 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
       v->fuse = 1;
       v->tile[0] = (int32_t)nmax;
     }
+  } else if (!march_offsets_fit(meshes, count)) {
+    // rows or planes beyond the march kernels' 32-bit offsets: LDS tiles
   } else if (d == 2) {
     bool periodic = true;
     for (int m = 0; m < count; ++m)

@@ -122,7 +122,29 @@ def test_default_variant(lib):
     assert pb.paraiso_default_variant([_mesh(1, (3408, 1, 1), pb.F64)]).lds == 1
     v1 = pb.paraiso_default_variant([_mesh(1, (100, 1, 1)), _mesh(1, (1000, 1, 1))])
     assert (v1.lds, v1.tile[0], v1.persistent) == (3, 1000, 1)
+    # the march kernels take 32-bit byte offsets within a row (2D) / plane (3D)
+    assert pb.paraiso_default_variant([_mesh(2, (1 << 29, 2, 1))]).lds == 2
+    assert pb.paraiso_default_variant([_mesh(2, (1 << 30, 1, 1))]).lds == 1
+    assert pb.paraiso_default_variant([_mesh(2, (1 << 29, 2, 1), pb.F64)]).lds == 1
+    assert pb.paraiso_default_variant([_mesh(3, (1 << 15, 1 << 14, 1))]).lds == 2
+    assert pb.paraiso_default_variant([_mesh(3, (1 << 15, 1 << 15, 1))]).lds == 1
 
 
 def test_version(lib):
     assert "gfx950" in pb.paraiso_version()
+
+
+def test_header_compiles_as_c_and_cpp(tmp_path):
+    # the boundary is plain C: the header must stand alone in C99 and C++17
+    import shutil
+    import subprocess
+    inc = os.path.join(ROOT, "include")
+    src = tmp_path / "use.c"
+    src.write_text('#include "paraiso.h"\nint main(void) { paraiso_variant v; (void)v; return PARAISO_OK; }\n')
+    for cc, std in (("gcc", "-std=c99"), ("g++", "-std=c++17")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not found")
+        lang = ["-x", "c++"] if cc == "g++" else []
+        r = subprocess.run([cc, std, "-Wall", "-Werror", "-fsyntax-only", "-I", inc] + lang + [str(src)],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
