@@ -26,6 +26,12 @@ _COUNT_PATH = os.path.join(_HERE, "liboracle_count.so")
 
 PERIODIC = 0
 OUTFLOW = 1
+ANALYTIC = 2
+
+# problems of the convergence tests (analytic boundaries)
+ENTROPY_WAVE = 1
+SOUND_WAVE = 2
+SHOCK_TUBE = 3
 
 OK = 0
 BAD_ARG = -1
@@ -58,6 +64,25 @@ class _Mesh(ctypes.Structure):
                 ("pad2_", ctypes.c_int32)]
 
 
+class _Analytic(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("angle", ctypes.c_double), ("amplitude", ctypes.c_double)]
+
+
+@dataclass
+class Analytic:
+    """A convergence-test problem on the unit square: kind, rotation angle of
+    the initial condition about the centre (radians), sound-wave amplitude."""
+    kind: int
+    angle: float = 0.0
+    amplitude: float = 1e-5
+
+    def c(self) -> _Analytic:
+        a = _Analytic()
+        a.kind, a.angle, a.amplitude = int(self.kind), float(self.angle), float(self.amplitude)
+        return a
+
+
 _lib = None
 
 
@@ -82,8 +107,20 @@ def _load():
         lib.orc_interpolate.argtypes = [ctypes.c_double] * 3 + [dp, dp]
         lib.orc_prim_of_cons.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
         lib.orc_cons_of_prim.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+        ap = ctypes.POINTER(_Analytic)
+        lib.orc_stage_t.argtypes = [mp, ap, ctypes.c_double, dp, dp, ctypes.c_double, dp]
+        lib.orc_step_t.argtypes = [mp, ap, ctypes.c_double, dp, ctypes.c_double, dp]
+        lib.orc_advance_t.argtypes = [mp, ap, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int64,
+                                      dp, ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_exact_prims.argtypes = [mp, ap, dp, ctypes.c_double, dp]
+        lib.orc_exact_state.argtypes = [mp, ap, ctypes.c_double, dp]
+        lib.orc_riemann_star.argtypes = [ctypes.c_double, dp, dp, dp, dp]
+        lib.orc_riemann_sample.argtypes = [ctypes.c_double, dp, dp, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, dp]
+        lib.orc_riemann_sample.restype = None
         for fn in ("orc_stage", "orc_step", "orc_cfl_qmax", "orc_cfl_dt", "orc_totals",
-                   "orc_advance"):
+                   "orc_advance", "orc_stage_t", "orc_step_t", "orc_advance_t", "orc_exact_prims", "orc_exact_state",
+                   "orc_riemann_star"):
             getattr(lib, fn).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -148,20 +185,27 @@ def _check(rc: int, what: str):
         raise OracleError(f"{what}: status {rc}")
 
 
-def stage(mesh: Mesh, U_in, U_base, cdt: float) -> np.ndarray:
+def _an(analytic):
+    return ctypes.byref(analytic.c()) if analytic is not None else None
+
+
+def stage(mesh: Mesh, U_in, U_base, cdt: float, t: float = 0.0, analytic: Analytic | None = None) -> np.ndarray:
+    """One stage; t (the time U_in stands for) only matters for analytic boundaries."""
     lib = _load()
     a, b = _as_state(mesh, U_in), _as_state(mesh, U_base)
     out = np.empty_like(a)
-    _check(lib.orc_stage(ctypes.byref(mesh._c), _ptr(a), _ptr(b), float(cdt), _ptr(out)), "stage")
+    _check(lib.orc_stage_t(ctypes.byref(mesh._c), _an(analytic), float(t), _ptr(a), _ptr(b), float(cdt),
+                           _ptr(out)), "stage")
     return out
 
 
-def step(mesh: Mesh, U0, dt: float) -> np.ndarray:
-    """One midpoint-RK2 step with the given dt (FP64)."""
+def step(mesh: Mesh, U0, dt: float, t: float = 0.0, analytic: Analytic | None = None) -> np.ndarray:
+    """One midpoint-RK2 step with the given dt (FP64) from time t."""
     lib = _load()
     a = _as_state(mesh, U0)
     out = np.empty_like(a)
-    _check(lib.orc_step(ctypes.byref(mesh._c), _ptr(a), float(dt), _ptr(out)), "step")
+    _check(lib.orc_step_t(ctypes.byref(mesh._c), _an(analytic), float(t), _ptr(a), float(dt), _ptr(out)),
+           "step")
     return out
 
 
@@ -189,15 +233,54 @@ def totals(mesh: Mesh, U) -> np.ndarray:
     return out
 
 
-def advance(mesh: Mesh, U0, cfl: float, t_end: float, max_steps: int = 1 << 40, t0: float = 0.0):
+def advance(mesh: Mesh, U0, cfl: float, t_end: float, max_steps: int = 1 << 40, t0: float = 0.0,
+            analytic: Analytic | None = None):
     """Advance a copy of U0 to t_end; returns (U, t, steps)."""
     lib = _load()
     U = _as_state(mesh, U0).copy()
     t = ctypes.c_double(t0)
     steps = ctypes.c_int64()
-    _check(lib.orc_advance(ctypes.byref(mesh._c), _ptr(U), float(cfl), float(t_end),
-                           int(max_steps), ctypes.byref(t), ctypes.byref(steps)), "advance")
+    _check(lib.orc_advance_t(ctypes.byref(mesh._c), _an(analytic), _ptr(U), float(cfl), float(t_end),
+                             int(max_steps), ctypes.byref(t), ctypes.byref(steps)), "advance")
     return U, t.value, steps.value
+
+
+# ---- exact solutions of the convergence-test problems ---------------------------------
+
+def exact_prims(mesh: Mesh, analytic: Analytic, x, t: float) -> np.ndarray:
+    """Primitive state (rho, v_a, p) of the problem at point x and time t."""
+    x = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+    v = np.zeros(mesh.nf)
+    _check(_load().orc_exact_prims(ctypes.byref(mesh._c), ctypes.byref(analytic.c()), _ptr(x), float(t),
+                                   _ptr(v)), "exact")
+    return v
+
+
+def exact_state(mesh: Mesh, analytic: Analytic, t: float) -> np.ndarray:
+    """Conserved state of the problem at every cell centre, in the oracle's layout."""
+    U = np.zeros(mesh.shape)
+    _check(_load().orc_exact_state(ctypes.byref(mesh._c), ctypes.byref(analytic.c()), float(t), _ptr(U)),
+           "exact")
+    return U
+
+
+def riemann_star(gamma: float, left, right) -> tuple[float, float]:
+    """(p*, u*) of the exact Riemann problem; states are (rho, u, p)."""
+    L = np.ascontiguousarray(left, dtype=np.float64)
+    R = np.ascontiguousarray(right, dtype=np.float64)
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    _check(_load().orc_riemann_star(float(gamma), _ptr(L), _ptr(R), ctypes.byref(ps), ctypes.byref(us)),
+           "riemann")
+    return ps.value, us.value
+
+
+def riemann_sample(gamma: float, left, right, xi: float) -> np.ndarray:
+    L = np.ascontiguousarray(left, dtype=np.float64)
+    R = np.ascontiguousarray(right, dtype=np.float64)
+    ps, us = riemann_star(gamma, L, R)
+    out = np.zeros(3)
+    _load().orc_riemann_sample(float(gamma), _ptr(L), _ptr(R), ps, us, float(xi), _ptr(out))
+    return out
 
 
 # ---- single-cell pieces, exposed for the unit pins -----------------------------------

@@ -30,8 +30,14 @@
  *
  * Structure is deliberately plain: every stage fills a ghost-padded copy of
  * the primitive field (2 ghost cells per side on every active axis; periodic
- * wrap or outflow copy of the edge cell), then makes whole-array passes:
- * faces of axis 0, faces of axis 1, ..., then the update.
+ * wrap, outflow copy of the edge cell, or the analytic solution of the
+ * problem at the cell centre and the stage's time), then makes whole-array
+ * passes: faces of axis 0, faces of axis 1, ..., then the update.
+ *
+ * Analytic boundaries follow the paper's convergence tests: on the unit
+ * square the analytic solution is substituted outside the solved domain.
+ * A stage reads its ghosts at the time its input state stands for: t for
+ * stage 1 (U0) and t + dt/2 for stage 2 (U1, the midpoint state).
  *
  * Layout of a state array: (d+2) fields, each a contiguous block of
  * nx*ny*nz doubles with x fastest: U[f*N + (k*ny + j)*nx + i].
@@ -50,6 +56,23 @@
 
 #define ORC_PERIODIC 0
 #define ORC_OUTFLOW 1
+#define ORC_ANALYTIC 2
+
+/* Problems of the convergence tests (paper: entropy wave, sound wave, Sod's
+ * shock tube).  Each is a function of s = (x - 1/2) cos(th) + (y - 1/2)
+ * sin(th) + 1/2, the coordinate along n = (cos th, sin th) ("coaxial": th =
+ * 0; "oblique": the initial condition rotated about the centre of the unit
+ * square by th), with the velocity along n. */
+#define ORC_ENTROPY_WAVE 1
+#define ORC_SOUND_WAVE 2
+#define ORC_SHOCK_TUBE 3
+
+typedef struct {
+  int32_t kind;
+  int32_t pad_;
+  double angle;     /* th, radians */
+  double amplitude; /* A of the sound wave */
+} orc_analytic;
 
 #define NGHOST 2
 
@@ -74,7 +97,7 @@ static int check_mesh(const orc_mesh* m) {
       continue;
     }
     if (!(m->dx[a] > 0.0) || !isfinite(m->dx[a])) return ORC_BAD_ARG;
-    if (m->bc[a] != ORC_PERIODIC && m->bc[a] != ORC_OUTFLOW) return ORC_BAD_ARG;
+    if (m->bc[a] != ORC_PERIODIC && m->bc[a] != ORC_OUTFLOW && m->bc[a] != ORC_ANALYTIC) return ORC_BAD_ARG;
   }
   return ORC_OK;
 }
@@ -199,6 +222,173 @@ void orc_hllc(int ndim, double gamma, int ax, const double* vl, const double* vr
   for (int q = 0; q < nf; ++q) f[q] = fk[q] + sk * (ustar[q] - uk[q]);
 }
 
+#ifndef ORC_COUNTING
+/* ---------------------------------------------------------------------- */
+/* Exact solutions of the convergence-test problems.                       */
+/* ---------------------------------------------------------------------- */
+
+/* Exact Riemann problem for the ideal gas (Toro, Riemann Solvers and
+ * Numerical Methods for Fluid Dynamics, ch. 4).  States are (rho, u, p)
+ * along the normal.  f_K(p) is the velocity change across the K wave: a
+ * shock for p > p_K, a rarefaction otherwise; p* solves
+ * f_L(p) + f_R(p) + u_R - u_L = 0 (Newton from the two-rarefaction guess),
+ * u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2. */
+static double wave_fn(double p, const double* k, double gamma, double* dfdp) {
+  const double rk = k[0], pk = k[2];
+  const double ck = sqrt(gamma * pk / rk);
+  if (p > pk) {
+    const double a = 2.0 / ((gamma + 1.0) * rk), b = (gamma - 1.0) / (gamma + 1.0) * pk;
+    const double q = sqrt(a / (p + b));
+    *dfdp = q * (1.0 - 0.5 * (p - pk) / (p + b));
+    return (p - pk) * q;
+  }
+  const double e = (gamma - 1.0) / (2.0 * gamma);
+  const double r = pow(p / pk, e);
+  *dfdp = r / (rk * ck * (p / pk));
+  return 2.0 * ck / (gamma - 1.0) * (r - 1.0);
+}
+
+int orc_riemann_star(double gamma, const double* L, const double* R, double* ps, double* us) {
+  const double cl = sqrt(gamma * L[2] / L[0]), cr = sqrt(gamma * R[2] / R[0]);
+  const double e = (gamma - 1.0) / (2.0 * gamma);
+  const double du = R[1] - L[1];
+  if (2.0 * (cl + cr) / (gamma - 1.0) <= du) return ORC_BAD_ARG; /* vacuum forms */
+  double p = pow((cl + cr - 0.5 * (gamma - 1.0) * du) / (cl / pow(L[2], e) + cr / pow(R[2], e)), 1.0 / e);
+  for (int it = 0; it < 100; ++it) {
+    double dl, dr;
+    const double g = wave_fn(p, L, gamma, &dl) + wave_fn(p, R, gamma, &dr) + du;
+    double pn = p - g / (dl + dr);
+    if (pn < 1e-300) pn = 1e-300;
+    const double change = fabs(pn - p) / (0.5 * (pn + p));
+    p = pn;
+    if (change < 1e-15) break;
+  }
+  double dl, dr;
+  *ps = p;
+  *us = 0.5 * (L[1] + R[1]) + 0.5 * (wave_fn(p, R, gamma, &dr) - wave_fn(p, L, gamma, &dl));
+  return ORC_OK;
+}
+
+/* The solution at x/t = xi: the left state, the left fan, the left star
+ * state, the right star state, the right fan or the right state. */
+void orc_riemann_sample(double gamma, const double* L, const double* R, double ps, double us, double xi,
+                        double* out) {
+  const double g1 = (gamma - 1.0) / (gamma + 1.0);
+  if (xi <= us) {
+    const double rk = L[0], uk = L[1], pk = L[2], ck = sqrt(gamma * pk / rk);
+    if (ps > pk) {
+      const double sk = uk - ck * sqrt((gamma + 1.0) / (2.0 * gamma) * ps / pk + (gamma - 1.0) / (2.0 * gamma));
+      if (xi <= sk) {
+        out[0] = rk; out[1] = uk; out[2] = pk;
+      } else {
+        out[0] = rk * (ps / pk + g1) / (g1 * ps / pk + 1.0); out[1] = us; out[2] = ps;
+      }
+    } else {
+      const double head = uk - ck, cs = ck * pow(ps / pk, (gamma - 1.0) / (2.0 * gamma)), tail = us - cs;
+      if (xi <= head) {
+        out[0] = rk; out[1] = uk; out[2] = pk;
+      } else if (xi > tail) {
+        out[0] = rk * pow(ps / pk, 1.0 / gamma); out[1] = us; out[2] = ps;
+      } else {
+        const double c = 2.0 / (gamma + 1.0) * (ck + 0.5 * (gamma - 1.0) * (uk - xi));
+        out[0] = rk * pow(c / ck, 2.0 / (gamma - 1.0));
+        out[1] = 2.0 / (gamma + 1.0) * (ck + 0.5 * (gamma - 1.0) * uk + xi);
+        out[2] = pk * pow(c / ck, 2.0 * gamma / (gamma - 1.0));
+      }
+    }
+  } else {
+    const double rk = R[0], uk = R[1], pk = R[2], ck = sqrt(gamma * pk / rk);
+    if (ps > pk) {
+      const double sk = uk + ck * sqrt((gamma + 1.0) / (2.0 * gamma) * ps / pk + (gamma - 1.0) / (2.0 * gamma));
+      if (xi >= sk) {
+        out[0] = rk; out[1] = uk; out[2] = pk;
+      } else {
+        out[0] = rk * (ps / pk + g1) / (g1 * ps / pk + 1.0); out[1] = us; out[2] = ps;
+      }
+    } else {
+      const double head = uk + ck, cs = ck * pow(ps / pk, (gamma - 1.0) / (2.0 * gamma)), tail = us + cs;
+      if (xi >= head) {
+        out[0] = rk; out[1] = uk; out[2] = pk;
+      } else if (xi < tail) {
+        out[0] = rk * pow(ps / pk, 1.0 / gamma); out[1] = us; out[2] = ps;
+      } else {
+        const double c = 2.0 / (gamma + 1.0) * (ck - 0.5 * (gamma - 1.0) * (uk - xi));
+        out[0] = rk * pow(c / ck, 2.0 / (gamma - 1.0));
+        out[1] = 2.0 / (gamma + 1.0) * (-ck + 0.5 * (gamma - 1.0) * uk + xi);
+        out[2] = pk * pow(c / ck, 2.0 * gamma / (gamma - 1.0));
+      }
+    }
+  }
+}
+
+/* Primitive state of problem `an` at point x (x[0..ndim-1]) and time t. */
+int orc_exact_prims(const orc_mesh* m, const orc_analytic* an, const double* x, double t, double* v) {
+  if (!m || !an) return ORC_BAD_ARG;
+  const int d = m->ndim;
+  const double gamma = m->gamma;
+  const double cth = d > 1 ? cos(an->angle) : 1.0, sth = d > 1 ? sin(an->angle) : 0.0;
+  if (d == 1 && an->angle != 0.0) return ORC_BAD_ARG;
+  const double s = (x[0] - 0.5) * cth + (d > 1 ? (x[1] - 0.5) * sth : 0.0) + 0.5;
+  double rho, vn, p;
+  const double pi = 3.14159265358979323846;
+  if (an->kind == ORC_ENTROPY_WAVE) {
+    /* rho = 2 + sin(2 pi x), v = 1, p = 1: carried unchanged at speed 1 */
+    rho = 2.0 + sin(2.0 * pi * (s - t));
+    vn = 1.0;
+    p = 1.0;
+  } else if (an->kind == ORC_SOUND_WAVE) {
+    /* rho = gamma (1 + A sin 2 pi x), v = A sin 2 pi x, p = 1 + gamma A sin 2 pi x:
+     * a right-going acoustic wave on rho = gamma, p = 1 (sound speed 1),
+     * exact to first order in A */
+    const double w = an->amplitude * sin(2.0 * pi * (s - t));
+    rho = gamma * (1.0 + w);
+    vn = w;
+    p = 1.0 + gamma * w;
+  } else if (an->kind == ORC_SHOCK_TUBE) {
+    const double L[3] = {1.0, 0.0, 1.0}, R[3] = {0.125, 0.0, 0.1};
+    if (!(t > 0.0)) {
+      const double* k = s < 0.5 ? L : R;
+      rho = k[0]; vn = k[1]; p = k[2];
+    } else {
+      double ps, us, out[3];
+      int rc = orc_riemann_star(gamma, L, R, &ps, &us);
+      if (rc) return rc;
+      orc_riemann_sample(gamma, L, R, ps, us, (s - 0.5) / t, out);
+      rho = out[0]; vn = out[1]; p = out[2];
+    }
+  } else {
+    return ORC_BAD_ARG;
+  }
+  v[0] = rho;
+  v[1] = vn * cth;
+  if (d > 1) v[2] = vn * sth;
+  if (d > 2) v[3] = 0.0;
+  v[d + 1] = p;
+  return ORC_OK;
+}
+
+/* The conserved state of problem `an` at every cell centre at time t. */
+int orc_exact_state(const orc_mesh* m, const orc_analytic* an, double t, double* U) {
+  int rc = check_mesh(m);
+  if (rc) return rc;
+  const int d = m->ndim, nf = d + 2;
+  const int64_t N = ncells(m);
+  for (int64_t k = 0; k < m->n[2]; ++k)
+    for (int64_t j = 0; j < m->n[1]; ++j)
+      for (int64_t i = 0; i < m->n[0]; ++i) {
+        const int64_t g[3] = {i, j, k};
+        double x[3], v[5], u[5];
+        for (int a = 0; a < d; ++a) x[a] = ((double)g[a] + 0.5) * m->dx[a];
+        rc = orc_exact_prims(m, an, x, t, v);
+        if (rc) return rc;
+        orc_cons_of_prim(d, m->gamma, v, u);
+        const int64_t c = (k * m->n[1] + j) * m->n[0] + i;
+        for (int q = 0; q < nf; ++q) U[q * N + c] = u[q];
+      }
+  return ORC_OK;
+}
+#endif
+
 /* ---------------------------------------------------------------------- */
 /* Ghost-padded primitive field.                                           */
 /* ---------------------------------------------------------------------- */
@@ -223,9 +413,16 @@ static int64_t map_index(int64_t g, int64_t n, int bc) {
   return g;
 }
 
-static int pad_prims(const orc_mesh* m, const double* U, padded* P) {
+static int pad_prims(const orc_mesh* m, const orc_analytic* an, double t, const double* U, padded* P) {
   const int d = m->ndim, nf = d + 2;
   const int64_t N = ncells(m);
+  int analytic = 0;
+  for (int a = 0; a < d; ++a) analytic |= (m->bc[a] == ORC_ANALYTIC);
+#ifdef ORC_COUNTING
+  if (analytic) return ORC_BAD_ARG;
+#else
+  if (analytic && !an) return ORC_BAD_ARG;
+#endif
   P->ndim = d;
   P->nf = nf;
   for (int a = 0; a < 3; ++a) {
@@ -239,14 +436,33 @@ static int pad_prims(const orc_mesh* m, const double* U, padded* P) {
   for (int64_t k = 0; k < P->p[2]; ++k)
     for (int64_t j = 0; j < P->p[1]; ++j)
       for (int64_t i = 0; i < P->p[0]; ++i) {
-        int64_t si = map_index(i - off[0], m->n[0], m->bc[0]);
-        int64_t sj = (d > 1) ? map_index(j - off[1], m->n[1], m->bc[1]) : 0;
-        int64_t sk = (d > 2) ? map_index(k - off[2], m->n[2], m->bc[2]) : 0;
+        const int64_t g[3] = {i - off[0], j - off[1], k - off[2]};
+        int64_t dst = (k * P->p[1] + j) * P->p[0] + i;
+        double v[5];
+        int outside = 0;
+        for (int a = 0; a < d; ++a)
+          outside |= (m->bc[a] == ORC_ANALYTIC && (g[a] < 0 || g[a] >= m->n[a]));
+#ifndef ORC_COUNTING
+        if (outside) {
+          /* analytic boundary: the solution at the ghost cell's centre */
+          double x[3];
+          for (int a = 0; a < d; ++a) x[a] = ((double)g[a] + 0.5) * m->dx[a];
+          int rc = orc_exact_prims(m, an, x, t, v);
+          if (rc) {
+            free(P->v);
+            return rc;
+          }
+          for (int q = 0; q < nf; ++q) P->v[q * P->np + dst] = v[q];
+          continue;
+        }
+#endif
+        int64_t si = map_index(g[0], m->n[0], m->bc[0]);
+        int64_t sj = (d > 1) ? map_index(g[1], m->n[1], m->bc[1]) : 0;
+        int64_t sk = (d > 2) ? map_index(g[2], m->n[2], m->bc[2]) : 0;
         int64_t src = (sk * m->n[1] + sj) * m->n[0] + si;
-        double u[5], v[5];
+        double u[5];
         for (int q = 0; q < nf; ++q) u[q] = U[q * N + src];
         orc_prim_of_cons(d, m->gamma, u, v);
-        int64_t dst = (k * P->p[1] + j) * P->p[0] + i;
         for (int q = 0; q < nf; ++q) P->v[q * P->np + dst] = v[q];
       }
   return ORC_OK;
@@ -256,15 +472,15 @@ static int pad_prims(const orc_mesh* m, const double* U, padded* P) {
 /* One stage: U_out = U_base + sum_a (cdt/dr_a)(F_a[i-1/2] - F_a[i+1/2]),   */
 /* fluxes from U_in.                                                       */
 /* ---------------------------------------------------------------------- */
-int orc_stage(const orc_mesh* m, const double* Uin, const double* Ubase, double cdt,
-              double* Uout) {
+int orc_stage_t(const orc_mesh* m, const orc_analytic* an, double t, const double* Uin,
+                const double* Ubase, double cdt, double* Uout) {
   int rc = check_mesh(m);
   if (rc) return rc;
   if (!Uin || !Ubase || !Uout) return ORC_BAD_ARG;
   const int d = m->ndim, nf = d + 2;
   const int64_t N = ncells(m);
   padded P;
-  rc = pad_prims(m, Uin, &P);
+  rc = pad_prims(m, an, t, Uin, &P);
   if (rc) return rc;
 
   double* acc = (double*)calloc((size_t)nf * (size_t)N, sizeof(double));
@@ -329,18 +545,28 @@ int orc_stage(const orc_mesh* m, const double* Uin, const double* Ubase, double 
   return ORC_OK;
 }
 
-/* One midpoint Runge-Kutta step with a given dt. */
-int orc_step(const orc_mesh* m, const double* U0, double dt, double* U2) {
+int orc_stage(const orc_mesh* m, const double* Uin, const double* Ubase, double cdt, double* Uout) {
+  return orc_stage_t(m, 0, 0.0, Uin, Ubase, cdt, Uout);
+}
+
+/* One midpoint Runge-Kutta step with a given dt from time t (t only
+ * matters for analytic boundaries: stage 1 at t, stage 2 at t + dt/2). */
+int orc_step_t(const orc_mesh* m, const orc_analytic* an, double t, const double* U0, double dt,
+               double* U2) {
   int rc = check_mesh(m);
   if (rc) return rc;
   if (!(dt >= 0.0) || !isfinite(dt)) return ORC_BAD_ARG;
   const int64_t total = (int64_t)(m->ndim + 2) * ncells(m);
   double* U1 = (double*)malloc(sizeof(double) * (size_t)total);
   if (!U1) return ORC_NOMEM;
-  rc = orc_stage(m, U0, U0, 0.5 * dt, U1);
-  if (!rc) rc = orc_stage(m, U1, U0, dt, U2);
+  rc = orc_stage_t(m, an, t, U0, U0, 0.5 * dt, U1);
+  if (!rc) rc = orc_stage_t(m, an, t + 0.5 * dt, U1, U0, dt, U2);
   free(U1);
   return rc;
+}
+
+int orc_step(const orc_mesh* m, const double* U0, double dt, double* U2) {
+  return orc_step_t(m, 0, 0.0, U0, dt, U2);
 }
 
 /* ---------------------------------------------------------------------- */
@@ -414,8 +640,8 @@ int orc_totals(const orc_mesh* m, const double* U, double* out) {
 /* ---------------------------------------------------------------------- */
 /* Advance to t_end with the CFL step clamped to the remaining time.       */
 /* ---------------------------------------------------------------------- */
-int orc_advance(const orc_mesh* m, double* U, double cfl, double t_end, int64_t max_steps,
-                double* t_inout, int64_t* steps_out) {
+int orc_advance_t(const orc_mesh* m, const orc_analytic* an, double* U, double cfl, double t_end,
+                  int64_t max_steps, double* t_inout, int64_t* steps_out) {
   int rc = check_mesh(m);
   if (rc) return rc;
   const int64_t total = (int64_t)(m->ndim + 2) * ncells(m);
@@ -428,7 +654,7 @@ int orc_advance(const orc_mesh* m, double* U, double cfl, double t_end, int64_t 
     rc = orc_cfl_dt(m, U, cfl, &dt);
     if (rc) break;
     if (dt > t_end - t) dt = t_end - t;
-    rc = orc_step(m, U, dt, W);
+    rc = orc_step_t(m, an, t, U, dt, W);
     if (rc) break;
     memcpy(U, W, sizeof(double) * (size_t)total);
     t += dt;
@@ -438,4 +664,9 @@ int orc_advance(const orc_mesh* m, double* U, double cfl, double t_end, int64_t 
   *t_inout = t;
   *steps_out = steps;
   return rc;
+}
+
+int orc_advance(const orc_mesh* m, double* U, double cfl, double t_end, int64_t max_steps,
+                double* t_inout, int64_t* steps_out) {
+  return orc_advance_t(m, 0, U, cfl, t_end, max_steps, t_inout, steps_out);
 }

@@ -399,3 +399,110 @@ def test_totals_exact_on_integers():
     U = np.arange(32, dtype=float).reshape(4, 2, 4)
     t = oracle.totals(m, U)
     np.testing.assert_array_equal(t, [28 / 8, 92 / 8, 156 / 8, 220 / 8])
+
+
+# ---- analytic boundaries: the paper's convergence-test problems --------------------
+
+def _unit_square(n, bc=2):
+    return oracle.Mesh(2, (n, n), 1.4, (bc, bc))
+
+
+def test_c_riemann_solver_matches_textbook_and_python_solver():
+    # two independent implementations of the textbook construction, and Toro's table
+    g = _golden("sod_star_toro.json")
+    ps, us = oracle.riemann_star(g["gamma"], g["left"], g["right"])
+    assert abs(ps - g["p_star"]) < 1e-5 and abs(us - g["u_star"]) < 1e-5
+    for left, right in (((1.0, 0.0, 1.0), (0.125, 0.0, 0.1)), ((1.0, -2.0, 0.4), (1.0, 2.0, 0.4)),
+                        ((1.0, 0.0, 1000.0), (1.0, 0.0, 0.01)), ((5.99924, 19.5975, 460.894),
+                                                                  (5.99242, -6.19633, 46.095))):
+        L, R = er.Side(*left), er.Side(*right)
+        w = er.waves(1.4, L, R)
+        ps, us = oracle.riemann_star(1.4, left, right)
+        assert abs(ps - w.p_star) <= 1e-10 * w.p_star and abs(us - w.u_star) <= 1e-10 * (abs(w.u_star) + 1)
+        for xi in np.linspace(-25.0, 25.0, 101):
+            want = er.sample(1.4, L, R, float(xi))
+            got = oracle.riemann_sample(1.4, left, right, float(xi))
+            np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12)
+
+
+def test_exact_problems_start_from_the_paper_initial_conditions():
+    m = _unit_square(8)
+    g = 1.4
+    for x in ((0.1, 0.2), (0.37, 0.81), (0.93, 0.5)):
+        e = oracle.exact_prims(m, oracle.Analytic(oracle.ENTROPY_WAVE), x, 0.0)
+        np.testing.assert_allclose(e, [2 + math.sin(2 * math.pi * x[0]), 1.0, 0.0, 1.0], rtol=1e-14)
+        A = 1e-5
+        s = oracle.exact_prims(m, oracle.Analytic(oracle.SOUND_WAVE, 0.0, A), x, 0.0)
+        w = A * math.sin(2 * math.pi * x[0])
+        np.testing.assert_allclose(s, [g * (1 + w), w, 0.0, 1 + g * w], rtol=1e-14, atol=1e-20)
+        sod = oracle.exact_prims(m, oracle.Analytic(oracle.SHOCK_TUBE), x, 0.0)
+        assert list(sod) == ([1.0, 0.0, 0.0, 1.0] if x[0] < 0.5 else [0.125, 0.0, 0.0, 0.1])
+    # "oblique": the coaxial field rotated about (1/2, 1/2) by 60 degrees, velocity rotated with it
+    th = math.pi / 3
+    for kind in (oracle.ENTROPY_WAVE, oracle.SOUND_WAVE, oracle.SHOCK_TUBE):
+        for x in ((0.1, 0.2), (0.37, 0.81), (0.93, 0.5)):
+            for t in (0.0, 0.05):
+                dx, dy = x[0] - 0.5, x[1] - 0.5
+                back = (0.5 + dx * math.cos(th) + dy * math.sin(th), 0.5 - dx * math.sin(th) + dy * math.cos(th))
+                co = oracle.exact_prims(m, oracle.Analytic(kind, 0.0), back, t)
+                ob = oracle.exact_prims(m, oracle.Analytic(kind, th), x, t)
+                assert abs(ob[0] - co[0]) < 1e-13 and abs(ob[3] - co[3]) < 1e-13
+                np.testing.assert_allclose(ob[1:3], co[1] * np.array([math.cos(th), math.sin(th)]), atol=1e-13)
+
+
+@pytest.mark.parametrize("angle", [0.0, math.pi / 3])
+def test_analytic_boundary_keeps_a_uniform_state_bitwise(angle):
+    # a sound wave of amplitude 0 is the uniform state (gamma, 0, 1): ghost
+    # values equal to the interior give fluxes that cancel exactly
+    m = _unit_square(12)
+    an = oracle.Analytic(oracle.SOUND_WAVE, angle, 0.0)
+    U = oracle.exact_state(m, an, 0.0)
+    out = oracle.step(m, U, 0.01, 0.3, an)
+    np.testing.assert_array_equal(out, U)
+
+
+def test_analytic_boundary_sod_equals_outflow_before_the_waves_arrive():
+    # until t = 0.125 the exact solution at the ends of the tube is the initial
+    # state, which is what the outflow copy of the edge cell holds
+    n = 256
+    an = oracle.Analytic(oracle.SHOCK_TUBE)
+    ma = oracle.Mesh(1, (n,), 1.4, (oracle.ANALYTIC,))
+    mo = oracle.Mesh(1, (n,), 1.4, (oracle.OUTFLOW,))
+    U0 = oracle.exact_state(ma, an, 0.0)
+    Ua, ta, na = oracle.advance(ma, U0, 0.5, 0.125, analytic=an)
+    Uo, to, no = oracle.advance(mo, U0, 0.5, 0.125)
+    assert na == no and ta == to == 0.125
+    np.testing.assert_allclose(Ua, Uo, rtol=0, atol=1e-13)
+
+
+def test_stage_two_reads_ghosts_at_the_midpoint_time():
+    # a stage is the same computation at any t except for its ghost values:
+    # stage 2 of a step from t uses the exact solution at t + dt/2
+    m = _unit_square(10)
+    an = oracle.Analytic(oracle.ENTROPY_WAVE, math.pi / 3)
+    U0 = oracle.exact_state(m, an, 0.2)
+    dt = 0.004
+    U1 = oracle.stage(m, U0, U0, 0.5 * dt, 0.2, an)
+    want = oracle.stage(m, U1, U0, dt, 0.2 + 0.5 * dt, an)
+    np.testing.assert_array_equal(oracle.step(m, U0, dt, 0.2, an), want)
+    assert np.max(np.abs(oracle.stage(m, U1, U0, dt, 0.2, an) - want)) > 1e-6
+
+
+def _l1_rho(m, an, t_end):
+    U0 = oracle.exact_state(m, an, 0.0)
+    U, t, _ = oracle.advance(m, U0, 0.5, t_end, analytic=an)
+    assert t == t_end
+    return float(np.mean(np.abs(U[0] - oracle.exact_state(m, an, t_end)[0])))
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("kind,angle", [(oracle.ENTROPY_WAVE, 0.0), (oracle.ENTROPY_WAVE, math.pi / 3),
+                                        (oracle.SOUND_WAVE, 0.0), (oracle.SOUND_WAVE, math.pi / 3)])
+def test_convergence_with_analytic_boundaries(kind, angle):
+    # the paper's convergence tests on the unit square, to t = 1: the L1 error
+    # of density falls at second order (minmod limiting clips the extrema, so
+    # slightly less)
+    an = oracle.Analytic(kind, angle, 1e-5)
+    errs = [_l1_rho(_unit_square(n), an, 1.0) for n in (32, 64, 128)]
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(o > 1.6 for o in orders), (errs, orders)
