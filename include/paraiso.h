@@ -54,6 +54,12 @@ extern "C" {
 /* boundary conditions per axis */
 #define PARAISO_PERIODIC 0               /* wrap-around */
 #define PARAISO_OUTFLOW 1                /* zero-gradient: ghost cells copy the edge cell's U */
+#define PARAISO_ANALYTIC 2               /* ghost cells hold an exact solution (paraiso_set_analytic) */
+
+/* exact solutions for PARAISO_ANALYTIC boundaries (paraiso_analytic.kind) */
+#define PARAISO_ENTROPY_WAVE 1
+#define PARAISO_SOUND_WAVE 2
+#define PARAISO_SHOCK_TUBE 3
 
 /* element types */
 #define PARAISO_F32 0
@@ -137,7 +143,7 @@ int32_t paraiso_workspace_bytes(const paraiso_mesh* meshes, int32_t count, size_
  * hipStream_t (NULL = the default stream).  The mesh descriptors are copied;
  * buffer 0 holds the initial state.
  * Errors: INVALID_ARG (null pointers, ndim not in 1..3, n < 1, gamma <= 1,
- * dx <= 0 or non-finite, bc not PERIODIC/OUTFLOW, overlapping buffers,
+ * dx <= 0 or non-finite, bc not PERIODIC/OUTFLOW/ANALYTIC, overlapping buffers,
  * mixed ndim/dtype in a batch), UNSUPPORTED (too many cells),
  * WORKSPACE (workspace too small), HIP.
  */
@@ -152,7 +158,8 @@ int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
 /* The default variant the library picks for these meshes (and applies in
  * paraiso_init): 1D the resident kernel when every mesh fits one
  * workgroup, else LDS tiles; 2D the fused register march when every mesh is
- * periodic on both axes, else LDS tiles; 3D the register march. */
+ * periodic on both axes, else LDS tiles; 3D the register march.  Any mesh
+ * with an analytic axis: unfused LDS tiles. */
 int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
 
 /*
@@ -167,8 +174,9 @@ int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
 /*
  * One midpoint-RK2 step of every mesh with the caller's time steps
  * dt[m] >= 0 (finite).  Reads the current buffer, writes the other one and
- * makes it current.  Asynchronous on the context's stream.
- * Errors: INVALID_ARG, HIP.
+ * makes it current; the device-held time advances by dt[m].  Asynchronous
+ * on the context's stream.
+ * Errors: INVALID_ARG (also: an analytic mesh without a problem set), HIP.
  */
 int32_t paraiso_step(paraiso_ctx* ctx, const double* dt);
 
@@ -184,6 +192,64 @@ int32_t paraiso_step(paraiso_ctx* ctx, const double* dt);
  */
 int32_t paraiso_advance(paraiso_ctx* ctx, double t_end, double cfl, int64_t max_steps,
                         double* t_inout, int64_t* steps_out);
+
+/*
+ * Analytic boundaries: the convergence tests of section "Tuning Experiments
+ * / Automated Tuning" (the convergence-test figure and the initial
+ * conditions given with it).  Cell i of axis a has its centre at
+ * x_a = (i + 1/2) dx[a] (the tests use the unit square, dx[a] = 1/n[a]).  On
+ * each axis whose bc is PARAISO_ANALYTIC, cells outside the mesh take the
+ * exact solution at their centres, evaluated in FP64 at the time the
+ * stage's input stands for:
+ * stage 1 at the step's time t, stage 2 at t + dt/2 (the midpoint state).
+ * With s = (x - 1/2) cos(angle) + (y - 1/2) sin(angle) + 1/2 and the
+ * velocity along n = (cos(angle), sin(angle), 0):
+ *   PARAISO_ENTROPY_WAVE  rho = 2 + sin 2 pi (s - t), |v| = 1, p = 1;
+ *   PARAISO_SOUND_WAVE    w = amplitude sin 2 pi (s - t): rho = gamma (1 + w),
+ *                         v_n = w, p = 1 + gamma w (sound speed 1; exact to
+ *                         first order in the amplitude);
+ *   PARAISO_SHOCK_TUBE    Sod's tube (1, 0, 1) | (0.125, 0, 0.1) split at
+ *                         s = 1/2, the exact Riemann solution at (s - 1/2)/t
+ *                         (the star state solved on the host in FP64).
+ * angle must be 0 in 1D ("coaxial"; the "oblique" tests use pi/3).
+ * Meshes with an analytic axis run on the unfused LDS-tile kernel
+ * (variant lds = 1, fuse = 0; the default picks it).
+ */
+typedef struct paraiso_analytic {
+  int32_t kind;      /* PARAISO_ENTROPY_WAVE, PARAISO_SOUND_WAVE or PARAISO_SHOCK_TUBE */
+  int32_t reserved;  /* 0 */
+  double angle;      /* radians; finite, 0 in 1D */
+  double amplitude;  /* sound wave: finite, |amplitude| < 1; ignored otherwise */
+} paraiso_analytic;
+
+/*
+ * Set the exact solution of mesh `mesh`, which must have a PARAISO_ANALYTIC
+ * axis.  Stepping a context with an analytic mesh whose problem is not set
+ * fails with INVALID_ARG.  Synchronous (uploads the mesh table).
+ * Errors: INVALID_ARG (null pointer, mesh out of range or without an
+ * analytic axis, kind, angle or amplitude out of range), HIP.
+ */
+int32_t paraiso_set_analytic(paraiso_ctx* ctx, int32_t mesh, const paraiso_analytic* an);
+
+/*
+ * Write the exact conserved state of mesh `mesh`'s problem at time t
+ * (finite) at every cell centre into its state buffer `buffer` (0 or 1):
+ * initial conditions and reference solutions of the convergence tests.
+ * Evaluated in FP64, rounded once to the element type.  Asynchronous on the
+ * context's stream.
+ * Errors: INVALID_ARG (null context, mesh or buffer out of range, no
+ * problem set), HIP.
+ */
+int32_t paraiso_exact_state(paraiso_ctx* ctx, int32_t mesh, double t, int32_t buffer);
+
+/*
+ * Simulation time of every mesh, t[m] (finite), kept on the device and
+ * advanced by paraiso_step and paraiso_advance; the analytic ghosts read it.
+ * paraiso_init starts it at 0; paraiso_advance starts it from t_inout.
+ * Synchronous.  Errors: INVALID_ARG, HIP.
+ */
+int32_t paraiso_set_time(paraiso_ctx* ctx, const double* t);
+int32_t paraiso_get_time(paraiso_ctx* ctx, double* t_out);
 
 /* Index (0 or 1) of the buffer holding the current state. */
 int32_t paraiso_current(const paraiso_ctx* ctx, int32_t* idx);

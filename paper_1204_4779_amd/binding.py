@@ -24,13 +24,18 @@ ERR_WORKSPACE = -5
 
 PERIODIC = 0
 OUTFLOW = 1
+ANALYTIC = 2
+ENTROPY_WAVE = 1
+SOUND_WAVE = 2
+SHOCK_TUBE = 3
 F32 = 0
 F64 = 1
 
 EXPORTS = ("paraiso_workspace_bytes", "paraiso_init", "paraiso_set_variant", "paraiso_get_variant",
            "paraiso_default_variant", "paraiso_cfl_dt", "paraiso_step", "paraiso_advance",
            "paraiso_current", "paraiso_totals", "paraiso_destroy", "paraiso_last_error",
-           "paraiso_version", "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
+           "paraiso_version", "paraiso_set_analytic", "paraiso_exact_state", "paraiso_set_time", "paraiso_get_time",
+           "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
            "paraiso_mlp_adam")
 
 
@@ -48,6 +53,17 @@ class paraiso_mesh(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("dx", ctypes.c_double * 3), ("gamma", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
                 ("reserved", ctypes.c_int32), ("state", (ctypes.c_void_p * 5) * 2)]
+
+
+class paraiso_analytic(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("angle", ctypes.c_double),
+                ("amplitude", ctypes.c_double)]
+
+    @classmethod
+    def make(cls, kind, angle=0.0, amplitude=0.0):
+        a = cls()
+        a.kind, a.reserved, a.angle, a.amplitude = int(kind), 0, float(angle), float(amplitude)
+        return a
 
 
 class paraiso_variant(ctypes.Structure):
@@ -98,6 +114,10 @@ def load(path: str | None = None):
         "paraiso_advance": ([vp, dbl, dbl, i64, dp, ctypes.POINTER(i64)], i32),
         "paraiso_current": ([vp, ctypes.POINTER(i32)], i32),
         "paraiso_totals": ([vp, dp], i32),
+        "paraiso_set_analytic": ([vp, i32, ctypes.POINTER(paraiso_analytic)], i32),
+        "paraiso_exact_state": ([vp, i32, dbl, i32], i32),
+        "paraiso_set_time": ([vp, dp], i32),
+        "paraiso_get_time": ([vp, dp], i32),
         "paraiso_destroy": ([vp], i32),
         "paraiso_last_error": ([], ctypes.c_char_p),
         "paraiso_version": ([], ctypes.c_char_p),
@@ -189,6 +209,24 @@ def paraiso_totals(ctx: int, count: int, nf: int) -> list:
     out = (ctypes.c_double * (count * nf))()
     _check(load().paraiso_totals(ctypes.c_void_p(ctx), out))
     return [list(out[m * nf:(m + 1) * nf]) for m in range(count)]
+
+
+def paraiso_set_analytic(ctx: int, mesh: int, an: paraiso_analytic) -> None:
+    _check(load().paraiso_set_analytic(ctypes.c_void_p(ctx), int(mesh), ctypes.byref(an)))
+
+
+def paraiso_exact_state(ctx: int, mesh: int, t: float, buffer: int) -> None:
+    _check(load().paraiso_exact_state(ctypes.c_void_p(ctx), int(mesh), float(t), int(buffer)))
+
+
+def paraiso_set_time(ctx: int, ts) -> None:
+    _check(load().paraiso_set_time(ctypes.c_void_p(ctx), _dbl_array(ts)))
+
+
+def paraiso_get_time(ctx: int, count: int = 1) -> list:
+    out = (ctypes.c_double * count)()
+    _check(load().paraiso_get_time(ctypes.c_void_p(ctx), out))
+    return list(out)
 
 
 def paraiso_destroy(ctx: int) -> None:
@@ -349,3 +387,18 @@ class Solver:
 
     def totals(self) -> list:
         return paraiso_totals(self.ctx, self.count, self.nf)
+
+    def set_analytic(self, kind: int, angle: float = 0.0, amplitude: float = 0.0, mesh: int = 0):
+        paraiso_set_analytic(self.ctx, mesh, paraiso_analytic.make(kind, angle, amplitude))
+
+    def fill_exact(self, t: float, mesh: int = 0, buffer: int | None = None):
+        """Exact state of the mesh's problem at time t into the current buffer (or `buffer`)."""
+        paraiso_exact_state(self.ctx, mesh, t, self.current() if buffer is None else buffer)
+
+    def set_time(self, ts):
+        if not isinstance(ts, (list, tuple)):
+            ts = [ts] * self.count
+        paraiso_set_time(self.ctx, ts)
+
+    def time(self) -> list:
+        return paraiso_get_time(self.ctx, self.count)

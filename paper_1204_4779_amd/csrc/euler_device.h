@@ -16,6 +16,7 @@ namespace paraiso {
 constexpr int kMaxFields = 5;
 constexpr int kPeriodic = 0;
 constexpr int kOutflow = 1;
+constexpr int kAnalytic = 2;  // ghosts from an exact solution (see Analytic)
 
 // ---------------------------------------------------------------------------
 // integer helpers

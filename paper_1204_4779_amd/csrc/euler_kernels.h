@@ -20,6 +20,17 @@
 
 namespace paraiso {
 
+// Problem whose exact solution fills the ghost cells of analytic boundaries
+// (the paper's convergence tests, on the unit square): a function of
+// s = (x - 1/2) cs + (y - 1/2) sn + 1/2 with the velocity along (cs, sn).
+struct Analytic {
+  int kind;              // 0 none, 1 entropy wave, 2 sound wave, 3 shock tube
+  int pad_;
+  double cs, sn;         // direction of the wave normal / tube axis
+  double amp;            // sound-wave amplitude
+  double ps, us;         // shock tube: star pressure and velocity (host-computed)
+};
+
 struct MeshDev {
   void* s[2][kMaxFields];  // the caller's two state buffers
   void* w[kMaxFields];     // stage-1 state (unfused variants), in the workspace
@@ -37,7 +48,78 @@ struct MeshDev {
   double gamma;
   double inv_gm1;          // 1 / (gamma - 1)
   double vol;              // cell volume
+  Analytic an;             // for meshes with an analytic boundary
 };
+
+// Exact primitive state of M.an at point (x, y) and time t, in FP64:
+//   entropy wave  rho = 2 + sin 2 pi (s - t), v_n = 1, p = 1;
+//   sound wave    w = A sin 2 pi (s - t): rho = gamma (1 + w), v_n = w,
+//                 p = 1 + gamma w (a right-going acoustic wave, sound speed 1);
+//   shock tube    (1, 0, 1) | (0.125, 0, 0.1) at s = 1/2, the exact Riemann
+//                 solution at (s - 1/2)/t: left state, left fan, left and
+//                 right star states, right fan or shock, right state.
+__device__ inline void riemann_side(double gamma, double rk, double uk, double pk, double ps, double us,
+                                    double xi, double sgn, double* o) {
+  // sgn = +1 for the left wave (sampled where xi <= u*), -1 for the right one
+  const double ck = sqrt(gamma * pk / rk);
+  const double g1 = (gamma - 1.0) / (gamma + 1.0);
+  if (ps > pk) {  // shock
+    const double sk = uk - sgn * ck * sqrt((gamma + 1.0) / (2.0 * gamma) * ps / pk + (gamma - 1.0) / (2.0 * gamma));
+    if (sgn * (xi - sk) <= 0.0) {
+      o[0] = rk; o[1] = uk; o[2] = pk;
+    } else {
+      o[0] = rk * (ps / pk + g1) / (g1 * ps / pk + 1.0); o[1] = us; o[2] = ps;
+    }
+  } else {        // rarefaction
+    const double head = uk - sgn * ck;
+    const double tail = us - sgn * ck * pow(ps / pk, (gamma - 1.0) / (2.0 * gamma));
+    if (sgn * (xi - head) <= 0.0) {
+      o[0] = rk; o[1] = uk; o[2] = pk;
+    } else if (sgn * (xi - tail) > 0.0) {
+      o[0] = rk * pow(ps / pk, 1.0 / gamma); o[1] = us; o[2] = ps;
+    } else {
+      const double c = 2.0 / (gamma + 1.0) * (ck + sgn * 0.5 * (gamma - 1.0) * (uk - xi));
+      o[0] = rk * pow(c / ck, 2.0 / (gamma - 1.0));
+      o[1] = 2.0 / (gamma + 1.0) * (sgn * ck + 0.5 * (gamma - 1.0) * uk + xi);
+      o[2] = pk * pow(c / ck, 2.0 * gamma / (gamma - 1.0));
+    }
+  }
+}
+
+template <typename T, int D>
+__device__ inline void exact_prims(const MeshDev& M, double x, double y, double t, T* v) {
+  const Analytic& A = M.an;
+  const double s = (x - 0.5) * A.cs + (D > 1 ? (y - 0.5) * A.sn : 0.0) + 0.5;
+  const double two_pi = 6.283185307179586;
+  double rho, vn, p;
+  if (A.kind == 1) {
+    rho = 2.0 + sin(two_pi * (s - t));
+    vn = 1.0;
+    p = 1.0;
+  } else if (A.kind == 2) {
+    const double w = A.amp * sin(two_pi * (s - t));
+    rho = M.gamma * (1.0 + w);
+    vn = w;
+    p = 1.0 + M.gamma * w;
+  } else {
+    double o[3];
+    if (!(t > 0.0)) {
+      o[0] = s < 0.5 ? 1.0 : 0.125; o[1] = 0.0; o[2] = s < 0.5 ? 1.0 : 0.1;
+    } else {
+      const double xi = (s - 0.5) / t;
+      if (xi <= A.us)
+        riemann_side(M.gamma, 1.0, 0.0, 1.0, A.ps, A.us, xi, 1.0, o);
+      else
+        riemann_side(M.gamma, 0.125, 0.0, 0.1, A.ps, A.us, xi, -1.0, o);
+    }
+    rho = o[0]; vn = o[1]; p = o[2];
+  }
+  v[0] = (T)rho;
+  v[1] = (T)(vn * A.cs);
+  if constexpr (D > 1) v[2] = (T)(vn * A.sn);
+  if constexpr (D > 2) v[3] = T(0);
+  v[D + 1] = (T)p;
+}
 
 struct Ctl {
   double t[3];
@@ -168,12 +250,12 @@ __device__ __forceinline__ double step_dt(const Args& a, int m, bool& active) {
 // Ring bookkeeping done once per mesh and step by the block owning tile 0.
 __device__ __forceinline__ void step_bookkeeping(const Args& a, int m, double dt, bool active) {
   const int nx = (a.ring + 1) % 3, nn = (a.ring + 2) % 3;
-  if (!a.dt) {
-    Ctl& c = a.ctl[m];
-    c.t[nx] = active ? c.t[a.ring] + dt : c.t[a.ring];
-    c.steps[nx] = c.steps[a.ring] + (active ? 1 : 0);
-    c.qbits[nn] = 0ull;
-  }
+  Ctl& c = a.ctl[m];
+  // t and the step count advance with explicit steps too (analytic
+  // boundaries read the time)
+  c.t[nx] = active ? c.t[a.ring] + dt : c.t[a.ring];
+  c.steps[nx] = c.steps[a.ring] + (active ? 1 : 0);
+  if (!a.dt) c.qbits[nn] = 0ull;
   if (m == 0 && a.queue) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) a.queue[nn * 16 + k] = 0u;
@@ -271,16 +353,22 @@ __device__ __forceinline__ int gidx(const MeshDev& M, int i, int j, int k) {
 // ---------------------------------------------------------------------------
 
 // t[ring] = t0[m], steps[ring] = 0, every CFL slot and queue counter cleared.
-static __global__ void k_ctl_init(Ctl* ctl, const double* t0, int nmeshes, int ring, unsigned int* queue) {
+// Reset the control ring at slot `ring`: the time from t0, or kept (keep = 1:
+// the time and step count in slot `ring` stay), or zero.
+static __global__ void k_ctl_init(Ctl* ctl, const double* t0, int nmeshes, int ring, unsigned int* queue,
+                                  int keep) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m < nmeshes) {
     Ctl& c = ctl[m];
+    const double t_old = c.t[ring];
+    const long long st_old = c.steps[ring];
     for (int s = 0; s < 3; ++s) {
       c.qbits[s] = 0ull;
       c.t[s] = 0.0;
       c.steps[s] = 0;
     }
-    c.t[ring] = t0 ? t0[m] : 0.0;
+    c.t[ring] = t0 ? t0[m] : (keep ? t_old : 0.0);
+    c.steps[ring] = (!t0 && keep) ? st_old : 0;
     c.flags = 0;
   }
   if (m < 48 && queue) queue[m] = 0u;
@@ -533,21 +621,32 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_direct(Args
 constexpr int kMaxR = 8;  // cells per thread kept in registers
 
 // Load U on the region `box` (origin org - H) into LDS primitives.
+// Cells outside the mesh on an analytic axis take the exact solution at
+// their centre and time t_ghost (the time the stage's input stands for).
 template <typename T, int D>
 __device__ __forceinline__ void lds_load_prims(const MeshDev& M, const Fields<T, D>& U, const Box& box,
                                                const int* org, int H, const Gas<T>& g, T* sV,
-                                               int vstride) {
+                                               int vstride, double t_ghost = 0.0) {
   for (int l = threadIdx.x; l < box.count; l += blockDim.x) {
     int i, j, k;
     box.coords(l, i, j, k);
-    const int gi = map_index(org[0] - H + i, M.n[0], M.bc[0]);
-    const int gj = D > 1 ? map_index(org[1] - H + j, M.n[1], M.bc[1]) : 0;
-    const int gk = D > 2 ? map_index(org[2] - H + k, M.n[2], M.bc[2]) : 0;
-    const int gc = gidx(M, gi, gj, gk);
-    T u[D + 2], v[D + 2];
+    const int r[3] = {org[0] - H + i, D > 1 ? org[1] - H + j : 0, D > 2 ? org[2] - H + k : 0};
+    bool ghost = false;
 #pragma unroll
-    for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][gc];
-    prim_of_cons<T, D>(u, v, g);
+    for (int a = 0; a < D; ++a) ghost |= M.bc[a] == kAnalytic && (r[a] < 0 || r[a] >= M.n[a]);
+    T v[D + 2];
+    if (ghost) {
+      exact_prims<T, D>(M, (r[0] + 0.5) * M.dx[0], D > 1 ? (r[1] + 0.5) * M.dx[1] : 0.0, t_ghost, v);
+    } else {
+      const int gi = map_index(r[0], M.n[0], M.bc[0]);
+      const int gj = D > 1 ? map_index(r[1], M.n[1], M.bc[1]) : 0;
+      const int gk = D > 2 ? map_index(r[2], M.n[2], M.bc[2]) : 0;
+      const int gc = gidx(M, gi, gj, gk);
+      T u[D + 2];
+#pragma unroll
+      for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][gc];
+      prim_of_cons<T, D>(u, v, g);
+    }
 #pragma unroll
     for (int q = 0; q < D + 2; ++q) sV[q * vstride + l] = v[q];
   }
@@ -646,8 +745,10 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
 #pragma unroll
       for (int q = 0; q < D + 2; ++q) acc[r][q] = T(0);
     if (active) {
+      // analytic ghosts: stage 1 reads U0 at time t, stage 2 the midpoint state at t + dt/2
+      const double t_ghost = a.ctl[t.m].t[a.ring] + (a.stage == 2 ? 0.5 * dt : 0.0);
       __syncthreads();  // previous item's readers of sV / sF are done
-      lds_load_prims<T, D>(M, Uin, G.vin, t.org, G.halo, g, sV, G.vstride);
+      lds_load_prims<T, D>(M, Uin, G.vin, t.org, G.halo, g, sV, G.vstride, t_ghost);
       __syncthreads();
       lds_all_axes<T, D>(G, G.tile, G.fx, G.vin, G.halo, sV, sF, g, coef, acc);
     }
@@ -836,6 +937,28 @@ __global__ void __launch_bounds__(256) k_totals_partial(Args a) {
     __syncthreads();
   }
   if (threadIdx.x < D + 2) a.partials[(size_t)chunk * kMaxFields + threadIdx.x] = s_sum[threadIdx.x][0];
+}
+
+// The exact conserved state of mesh m's analytic problem at time t, at every
+// cell centre, into state buffer `buf` (prims and conversion in FP64).
+template <typename T, int D>
+__global__ void __launch_bounds__(256) k_exact_state(Args a, int m, double t, int buf) {
+  const MeshDev& M = a.meshes[m];
+  const Fields<T, D> U = fields<T, D>(M.s[buf]);
+  const int c = blockIdx.x * 256 + (int)threadIdx.x;
+  if (c >= M.ncells) return;
+  const int i = c % M.n[0];
+  const int j = (c / M.n[0]) % M.n[1];
+  double v[D + 2];
+  exact_prims<double, D>(M, (i + 0.5) * M.dx[0], D > 1 ? (j + 0.5) * M.dx[1] : 0.0, t, v);
+  double ke = 0.0;
+  U.f[0][c] = (T)v[0];
+#pragma unroll
+  for (int q = 1; q <= D; ++q) {
+    U.f[q][c] = (T)(v[0] * v[q]);
+    ke += v[q] * v[q];
+  }
+  U.f[D + 1][c] = (T)(v[D + 1] * M.inv_gm1 + 0.5 * v[0] * ke);
 }
 
 // One block per mesh: out[m*(D+2)+q] = vol * sum of the mesh's partials.

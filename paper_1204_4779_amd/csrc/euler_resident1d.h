@@ -91,8 +91,9 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   }
   const bool explicit_dt = a.dt != nullptr;
   Ctl& c = a.ctl[m];
-  double t = explicit_dt ? 0.0 : c.t[a.ring];
-  long long steps = explicit_dt ? 0 : c.steps[a.ring];
+  double t = c.t[a.ring];
+  long long steps = c.steps[a.ring];
+  const long long steps0 = steps;
   double qmax = explicit_dt ? 0.0 : __longlong_as_double((long long)c.qbits[a.ring]);
   const double t_end = explicit_dt ? 0.0 : a.prm->t_end;
   const long long max_steps = explicit_dt ? 1 : a.prm->max_steps;
@@ -101,7 +102,7 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   for (;;) {
     double dt;
     if (explicit_dt) {
-      if (steps >= 1) break;
+      if (steps > steps0) break;
       dt = a.dt[m];
     } else {
       if (!(t < t_end) || steps >= max_steps || bad) break;
@@ -148,13 +149,15 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     }
   }
   if (m == 0 && tid < 16 && a.queue) a.queue[((a.ring + 2) % 3) * 16 + tid] = 0u;
-  if (!explicit_dt && tid == 0) {
+  if (tid == 0) {
     const int nx = (a.ring + 1) % 3, nn = (a.ring + 2) % 3;
     c.t[nx] = t;
     c.steps[nx] = steps;
-    c.qbits[nx] = (unsigned long long)__double_as_longlong(qmax);
-    c.qbits[nn] = 0ull;
-    if (bad) c.flags |= 1;
+    if (!explicit_dt) {
+      c.qbits[nx] = (unsigned long long)__double_as_longlong(qmax);
+      c.qbits[nn] = 0ull;
+      if (bad) c.flags |= 1;
+    }
   }
 }
 

@@ -21,6 +21,7 @@ const KernelTable* table_f32_1() {
       (const void*)k_cfl<float, 1>,
       (const void*)k_totals_partial<float, 1>,
       (const void*)k_totals_final<1>,
+      (const void*)k_exact_state<float, 1>,
       (int)sizeof(float),
   };
   return &t;

@@ -23,6 +23,7 @@ const KernelTable* table_f32_2() {
       (const void*)k_cfl<float, 2>,
       (const void*)k_totals_partial<float, 2>,
       (const void*)k_totals_final<2>,
+      (const void*)k_exact_state<float, 2>,
       (int)sizeof(float),
   };
   return &t;

@@ -22,6 +22,7 @@ const KernelTable* table_f32_3() {
       (const void*)k_cfl<float, 3>,
       (const void*)k_totals_partial<float, 3>,
       (const void*)k_totals_final<3>,
+      (const void*)k_exact_state<float, 3>,
       (int)sizeof(float),
   };
   return &t;

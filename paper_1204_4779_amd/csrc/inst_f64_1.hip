@@ -21,6 +21,7 @@ const KernelTable* table_f64_1() {
       (const void*)k_cfl<double, 1>,
       (const void*)k_totals_partial<double, 1>,
       (const void*)k_totals_final<1>,
+      (const void*)k_exact_state<double, 1>,
       (int)sizeof(double),
   };
   return &t;

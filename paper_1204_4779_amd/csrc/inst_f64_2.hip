@@ -23,6 +23,7 @@ const KernelTable* table_f64_2() {
       (const void*)k_cfl<double, 2>,
       (const void*)k_totals_partial<double, 2>,
       (const void*)k_totals_final<2>,
+      (const void*)k_exact_state<double, 2>,
       (int)sizeof(double),
   };
   return &t;

@@ -22,6 +22,7 @@ const KernelTable* table_f64_3() {
       (const void*)k_cfl<double, 3>,
       (const void*)k_totals_partial<double, 3>,
       (const void*)k_totals_final<3>,
+      (const void*)k_exact_state<double, 3>,
       (int)sizeof(double),
   };
   return &t;

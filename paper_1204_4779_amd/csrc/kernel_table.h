@@ -18,6 +18,7 @@ struct KernelTable {
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;
+  const void* exact_state;       // exact solution of an analytic problem into a state buffer
   int elem_bytes;
 };
 

@@ -56,6 +56,59 @@ const KernelTable* table_for(int dtype, int ndim) {
 
 int64_t cells_of(const paraiso_mesh& m) { return m.n[0] * m.n[1] * m.n[2]; }
 
+bool has_analytic(const paraiso_mesh& m) {
+  for (int a = 0; a < m.ndim; ++a)
+    if (m.bc[a] == PARAISO_ANALYTIC) return true;
+  return false;
+}
+
+bool any_analytic(const paraiso_mesh* ms, int count) {
+  for (int i = 0; i < count; ++i)
+    if (has_analytic(ms[i])) return true;
+  return false;
+}
+
+// Star state of the ideal-gas Riemann problem (rho, u, p)_L | (rho, u, p)_R
+// (Toro, Riemann Solvers and Numerical Methods for Fluid Dynamics, ch. 4):
+// p* is the root of phi(p) = g_L(p) + g_R(p) + u_R - u_L, where g_K is the
+// velocity jump across the K wave (shock above p_K, rarefaction below);
+// Newton's method from the acoustic (linearised) estimate.  u* follows from
+// either side.  Returns false if the data generate a vacuum.
+bool riemann_star_state(double gamma, const double L[3], const double R[3], double* ps, double* us) {
+  const double gp = gamma + 1.0, gm = gamma - 1.0;
+  auto jump = [&](const double K[3], double p, double& slope) {
+    const double c = std::sqrt(gamma * K[2] / K[0]);
+    if (p <= K[2]) {
+      const double r = std::pow(p / K[2], gm / (2.0 * gamma));
+      slope = r / (K[0] * c * (p / K[2]));
+      return 2.0 * c / gm * (r - 1.0);
+    }
+    const double A = 2.0 / (gp * K[0]), B = gm / gp * K[2];
+    const double root = std::sqrt(A / (B + p));
+    slope = root * (1.0 - 0.5 * (p - K[2]) / (B + p));
+    return root * (p - K[2]);
+  };
+  const double cL = std::sqrt(gamma * L[2] / L[0]), cR = std::sqrt(gamma * R[2] / R[0]);
+  const double du = R[1] - L[1];
+  if (2.0 * (cL + cR) / gm <= du) return false;
+  double p = 0.5 * (L[2] + R[2]) - 0.125 * du * (L[0] + R[0]) * (cL + cR);
+  p = std::max(p, 1e-8 * std::min(L[2], R[2]));
+  for (int it = 0; it < 200; ++it) {
+    double sL, sR;
+    const double phi = jump(L, p, sL) + jump(R, p, sR) + du;
+    double next = p - phi / (sL + sR);
+    if (!(next > 0.0)) next = 0.5 * p;
+    const bool done = std::fabs(next - p) <= 1e-15 * 0.5 * (next + p);
+    p = next;
+    if (done) break;
+  }
+  double sL, sR;
+  const double gL = jump(L, p, sL), gR = jump(R, p, sR);
+  *ps = p;
+  *us = 0.5 * (L[1] + R[1] + gR - gL);
+  return true;
+}
+
 int validate_mesh(const paraiso_mesh& m, int idx) {
   const std::string w = "mesh " + std::to_string(idx) + ": ";
   if (m.ndim < 1 || m.ndim > 3) return fail(PARAISO_ERR_INVALID_ARG, w + "ndim must be 1, 2 or 3");
@@ -71,8 +124,8 @@ int validate_mesh(const paraiso_mesh& m, int idx) {
     }
     if (!(m.dx[a] > 0.0) || !std::isfinite(m.dx[a]))
       return fail(PARAISO_ERR_INVALID_ARG, w + "dx[a] must be finite and > 0");
-    if (m.bc[a] != PARAISO_PERIODIC && m.bc[a] != PARAISO_OUTFLOW)
-      return fail(PARAISO_ERR_INVALID_ARG, w + "bc[a] must be PARAISO_PERIODIC or PARAISO_OUTFLOW");
+    if (m.bc[a] != PARAISO_PERIODIC && m.bc[a] != PARAISO_OUTFLOW && m.bc[a] != PARAISO_ANALYTIC)
+      return fail(PARAISO_ERR_INVALID_ARG, w + "bc[a] must be PARAISO_PERIODIC, PARAISO_OUTFLOW or PARAISO_ANALYTIC");
   }
   if (m.n[0] > (1 << 30) || m.n[1] > (1 << 30) || m.n[2] > (1 << 30) || cells_of(m) >= (int64_t(1) << 31))
     return fail(PARAISO_ERR_UNSUPPORTED, w + "more than 2^31 - 1 cells");
@@ -174,6 +227,8 @@ struct paraiso_ctx {
   int cur = 0, ring = 0;
   hipGraphExec_t graph[6] = {};
   int device = 0, num_cus = 0, max_lds = 0;
+  bool ctl_ready = false;          // the control ring holds a time to keep
+  std::vector<char> analytic_set;  // per mesh: problem given by paraiso_set_analytic
 };
 
 namespace {
@@ -280,10 +335,11 @@ int run_steps(paraiso_ctx* c, int64_t n) {
   return PARAISO_OK;
 }
 
+// Reset the control ring: time from d_t0 (device), else the time held so far.
 int ctl_init(paraiso_ctx* c, const double* d_t0) {
   const int blocks = (std::max(c->count, 48) + 255) / 256;
   hipLaunchKernelGGL(k_ctl_init, dim3(blocks), dim3(256), 0, c->stream, c->d_ctl, d_t0, c->count, c->ring,
-                     c->d_queue);
+                     c->d_queue, c->ctl_ready ? 1 : 0);
   HIP_TRY(hipGetLastError());
   return PARAISO_OK;
 }
@@ -352,6 +408,9 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
         return why = "3D register march: threads must be 64 * tile[1]", PARAISO_ERR_UNSUPPORTED;
     }
   }
+  if (any_analytic(c->meshes.data(), c->count) && (v.lds != 1 || v.fuse != 0))
+    return why = "analytic boundaries run on the unfused LDS-tile kernel (lds = 1, fuse = 0)",
+           PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
@@ -538,7 +597,9 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
   const int d = meshes[0].ndim;
   const bool f64 = meshes[0].dtype == PARAISO_F64;
   lds_variant(d, v);
-  if (d == 1) {
+  if (any_analytic(meshes, count)) {
+    v->fuse = 0;  // ghosts at each stage's own time
+  } else if (d == 1) {
     int64_t nmax = 1;
     for (int m = 0; m < count; ++m) nmax = std::max<int64_t>(nmax, meshes[m].n[0]);
     const size_t esize = f64 ? 8 : 4;
@@ -570,6 +631,15 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
     v->threads = 256;
   }
   if (count > 1) v->persistent = 1;
+}
+
+// Every analytic mesh needs its exact solution before it can be stepped.
+int check_problems(const paraiso_ctx* c) {
+  for (int m = 0; m < c->count; ++m)
+    if (has_analytic(c->meshes[m]) && !c->analytic_set[m])
+      return fail(PARAISO_ERR_INVALID_ARG,
+                  "mesh " + std::to_string(m) + ": analytic boundary without a problem (paraiso_set_analytic)");
+  return PARAISO_OK;
 }
 
 }  // namespace
@@ -673,6 +743,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   if (rc == PARAISO_ERR_UNSUPPORTED) {
     // a device with less LDS than gfx950: the LDS-tile family always applies
     lds_variant(c->ndim, &v);
+    if (any_analytic(meshes, count)) v.fuse = 0;
     if (count > 1) v.persistent = 1;
     rc = apply_variant(c, v);
   }
@@ -681,6 +752,8 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   if (rc) return bail(rc);
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
+  c->ctl_ready = true;
+  c->analytic_set.assign(count, 0);
   *out = c;
   return PARAISO_OK;
 }
@@ -731,6 +804,7 @@ int32_t paraiso_cfl_dt(paraiso_ctx* c, double cfl, double* dt_out) {
 
 int32_t paraiso_step(paraiso_ctx* c, const double* dt) {
   if (!c || !dt) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (int rc0 = check_problems(c)) return rc0;
   for (int m = 0; m < c->count; ++m)
     if (!(dt[m] >= 0.0) || !std::isfinite(dt[m])) return fail(PARAISO_ERR_INVALID_ARG, "dt must be finite and >= 0");
   HIP_TRY(hipMemcpyAsync(c->d_dt, dt, sizeof(double) * c->count, hipMemcpyHostToDevice, c->stream));
@@ -744,6 +818,7 @@ int32_t paraiso_step(paraiso_ctx* c, const double* dt) {
 int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_steps, double* t_inout,
                         int64_t* steps_out) {
   if (!c || !t_inout || !steps_out) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (int rc0 = check_problems(c)) return rc0;
   if (!(cfl > 0.0 && cfl <= 1.0)) return fail(PARAISO_ERR_INVALID_ARG, "cfl must be in (0, 1]");
   if (max_steps < 0) return fail(PARAISO_ERR_INVALID_ARG, "max_steps must be >= 0");
   if (std::isnan(t_end) || t_end == -INFINITY) return fail(PARAISO_ERR_INVALID_ARG, "t_end must be a number or +inf");
@@ -811,6 +886,69 @@ int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_st
     t_inout[m] = h[m].t[c->ring];
     steps_out[m] = h[m].steps[c->ring];
   }
+  return PARAISO_OK;
+}
+
+int32_t paraiso_set_analytic(paraiso_ctx* c, int32_t mesh, const paraiso_analytic* an) {
+  if (!c || !an) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (mesh < 0 || mesh >= c->count) return fail(PARAISO_ERR_INVALID_ARG, "mesh index out of range");
+  const paraiso_mesh& pm = c->meshes[mesh];
+  if (!has_analytic(pm)) return fail(PARAISO_ERR_INVALID_ARG, "mesh has no PARAISO_ANALYTIC axis");
+  if (an->kind != PARAISO_ENTROPY_WAVE && an->kind != PARAISO_SOUND_WAVE && an->kind != PARAISO_SHOCK_TUBE)
+    return fail(PARAISO_ERR_INVALID_ARG, "kind must be PARAISO_ENTROPY_WAVE, PARAISO_SOUND_WAVE or PARAISO_SHOCK_TUBE");
+  if (!std::isfinite(an->angle)) return fail(PARAISO_ERR_INVALID_ARG, "angle must be finite");
+  if (pm.ndim == 1 && an->angle != 0.0) return fail(PARAISO_ERR_INVALID_ARG, "angle must be 0 in 1D");
+  if (an->kind == PARAISO_SOUND_WAVE && !(std::fabs(an->amplitude) < 1.0))
+    return fail(PARAISO_ERR_INVALID_ARG, "sound-wave amplitude must be finite with |amplitude| < 1");
+  Analytic A{};
+  A.kind = an->kind;
+  A.cs = pm.ndim > 1 ? std::cos(an->angle) : 1.0;
+  A.sn = pm.ndim > 1 ? std::sin(an->angle) : 0.0;
+  A.amp = an->kind == PARAISO_SOUND_WAVE ? an->amplitude : 0.0;
+  if (an->kind == PARAISO_SHOCK_TUBE) {
+    const double L[3] = {1.0, 0.0, 1.0}, R[3] = {0.125, 0.0, 0.1};
+    if (!riemann_star_state(pm.gamma, L, R, &A.ps, &A.us))
+      return fail(PARAISO_ERR_INVALID_ARG, "shock tube: vacuum forms for this gamma");
+  }
+  c->hm[mesh].an = A;
+  HIP_TRY(hipMemcpyAsync(&c->d_meshes[mesh], &c->hm[mesh], sizeof(MeshDev), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->analytic_set[mesh] = 1;
+  return PARAISO_OK;
+}
+
+int32_t paraiso_exact_state(paraiso_ctx* c, int32_t mesh, double t, int32_t buffer) {
+  if (!c) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  if (mesh < 0 || mesh >= c->count) return fail(PARAISO_ERR_INVALID_ARG, "mesh index out of range");
+  if (buffer != 0 && buffer != 1) return fail(PARAISO_ERR_INVALID_ARG, "buffer must be 0 or 1");
+  if (!std::isfinite(t)) return fail(PARAISO_ERR_INVALID_ARG, "t must be finite");
+  if (!c->analytic_set[mesh]) return fail(PARAISO_ERR_INVALID_ARG, "mesh has no analytic problem set");
+  Args a = base_args(c);
+  int m = mesh, b = buffer;
+  void* args[] = {(void*)&a, (void*)&m, (void*)&t, (void*)&b};
+  const int64_t cells = cells_of(c->meshes[mesh]);
+  HIP_TRY(hipLaunchKernel(c->tab->exact_state, dim3((unsigned)((cells + 255) / 256)), dim3(256), args, 0,
+                          c->stream));
+  return PARAISO_OK;
+}
+
+int32_t paraiso_set_time(paraiso_ctx* c, const double* t) {
+  if (!c || !t) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  for (int m = 0; m < c->count; ++m)
+    if (!std::isfinite(t[m])) return fail(PARAISO_ERR_INVALID_ARG, "t must be finite");
+  HIP_TRY(hipMemcpyAsync(c->d_dt, t, sizeof(double) * c->count, hipMemcpyHostToDevice, c->stream));
+  int rc = ctl_init(c, c->d_dt);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return PARAISO_OK;
+}
+
+int32_t paraiso_get_time(paraiso_ctx* c, double* t_out) {
+  if (!c || !t_out) return fail(PARAISO_ERR_INVALID_ARG, "null argument");
+  std::vector<Ctl> h(c->count);
+  HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int m = 0; m < c->count; ++m) t_out[m] = h[m].t[c->ring];
   return PARAISO_OK;
 }
 

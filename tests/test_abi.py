@@ -58,7 +58,7 @@ def test_workspace_bytes_valid(lib):
 
 @pytest.mark.parametrize("bad", [
     dict(ndim=0), dict(ndim=4), dict(gamma=1.0), dict(gamma=float("nan")), dict(n=(0, 8, 1)),
-    dict(ndim=2, n=(8, 8, 2)), dict(bc=(2, 0, 0)), dict(dtype=7), dict(dx=(0.0, 1.0, 1.0)),
+    dict(ndim=2, n=(8, 8, 2)), dict(bc=(3, 0, 0)), dict(bc=(0, -1, 0)), dict(dtype=7), dict(dx=(0.0, 1.0, 1.0)),
     dict(dx=(float("inf"), 1.0, 1.0)),
 ])
 def test_workspace_bytes_rejects_invalid_mesh(lib, bad):
@@ -128,6 +128,12 @@ def test_default_variant(lib):
     assert pb.paraiso_default_variant([_mesh(2, (1 << 29, 2, 1), pb.F64)]).lds == 1
     assert pb.paraiso_default_variant([_mesh(3, (1 << 15, 1 << 14, 1))]).lds == 2
     assert pb.paraiso_default_variant([_mesh(3, (1 << 15, 1 << 15, 1))]).lds == 1
+    # any analytic axis: the unfused LDS-tile kernel (ghosts at each stage's own time)
+    for d, n in ((1, (64, 1, 1)), (2, (8, 8, 1)), (3, (4, 4, 4))):
+        v = pb.paraiso_default_variant([_mesh(d, n, bc=(pb.ANALYTIC, 0, 0))])
+        assert (v.lds, v.fuse) == (1, 0), d
+    v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, pb.ANALYTIC, 0))])
+    assert (v.lds, v.fuse, v.persistent) == (1, 0, 1)
 
 
 def test_version(lib):
