@@ -44,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes, each scaled by the reading of a plain 512 MiB device copy
 # (factors 2.000 and 1.000); valid only for the kernel sources they were taken
 # on (hash of the device headers) and the variant named.
-TRAFFIC = {"sources": "7d19485c2edf945f",
+TRAFFIC = {"sources": "41c1316fe71dbf50",
            "variant": {"tile": [64, 20], "lds": 2, "fuse": 1, "waves_per_eu": 0, "threads": 256},
            "bytes_per_launch": 157.8e6}
 
@@ -162,7 +162,7 @@ def calibration_copy():
     log("calibration copy: 536870912 bytes read and written per launch, 3 launches")
 
 
-def other_workload(name: str, steps: int, warmup: int):
+def other_workload(name: str, steps: int, warmup: int, sizes=None, with_cpu: bool = True):
     """Cell-updates/s of the other configurations (one JSON line each, not the headline)."""
     from paper_1204_4779_amd import binding as pb
     from paper_1204_4779_amd import inputs
@@ -202,7 +202,82 @@ def other_workload(name: str, steps: int, warmup: int):
                 "hbm_frac": v * bytes_per_cell_update(2, 4) / 1e9 / HBM_PEAK_GBS,
                 "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS["f32"],
                 "audit_drift": r["mass_energy_drift"]}
+    if name == "convergence":
+        return convergence_study(tuple(sizes) if sizes else (16, 32, 64, 128, 256, 512, 1024), with_cpu)
     raise SystemExit(f"unknown workload {name}")
+
+
+def convergence_study(sizes=(16, 32, 64, 128, 256, 512, 1024), with_cpu: bool = True):
+    """The convergence tests on the unit square with analytic boundaries:
+    entropy wave and sound wave (amplitude 1e-5) to t = 1, Sod's tube to
+    t = 0.125, each coaxial and rotated by 60 degrees, N^2 cells for N in
+    `sizes`, in FP64 and FP32.  Initial and reference states come from the
+    library's exact-state kernel; the L1 norm of the density error is taken
+    with torch.  Throughput: cell-updates of the largest-N runs over their
+    device time (advance, CFL included)."""
+    import torch
+    from paper_1204_4779_amd import binding as pb
+    problems = (("entropy", pb.ENTROPY_WAVE, 1.0), ("sound", pb.SOUND_WAVE, 1.0), ("sod", pb.SHOCK_TUBE, 0.125))
+    table, perf = {}, {}
+    for dtype in ("f64", "f32"):
+        var = variants.TUNED.get(("convergence", dtype))
+        big_cu, big_ms = 0.0, 0.0
+        for pname, kind, t_end in problems:
+            for tag, angle in (("coaxial", 0.0), ("oblique", math.pi / 3)):
+                errs, steps = [], []
+                for n in sizes:
+                    s = pb.Solver(pb.MeshSpec(2, (n, n), 1.4, (pb.ANALYTIC, pb.ANALYTIC)), dtype)
+                    s.set_analytic(kind, angle, 1e-5)
+                    if var:
+                        s.set_variant(var)
+                    s.fill_exact(0.0)
+                    a = torch.cuda.Event(enable_timing=True)
+                    b = torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    a.record(s.stream)
+                    t, k = s.advance(t_end, CFL)
+                    b.record(s.stream)
+                    torch.cuda.synchronize()
+                    ms = a.elapsed_time(b)
+                    rho = s.state()[0].double().clone()
+                    s.fill_exact(t_end)
+                    exact = s.state()[0].double()
+                    errs.append(float((rho - exact).abs().mean()))
+                    steps.append(k[0])
+                    if n == sizes[-1]:
+                        big_cu += float(n * n * k[0])
+                        big_ms += ms
+                    s.close()
+                orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+                table[f"{dtype}_{pname}_{tag}"] = {"N": list(sizes), "l1_rho": errs, "orders": orders, "steps": steps}
+                log(f"{dtype} {pname} {tag}: L1 {['%.3e' % e for e in errs]} orders {['%.2f' % o for o in orders]}")
+        v = big_cu / (big_ms / 1e3)
+        esz = 4 if dtype == "f32" else 8
+        perf[dtype] = {"value": v, "device_ms_n1024": big_ms, "variant": var or "library default",
+                       "hbm_frac": v * bytes_per_cell_update(2, esz) / 1e9 / HBM_PEAK_GBS,
+                       "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS[dtype]}
+    out = {"workload": f"convergence_tests_2d_unit_square_analytic_bc_N{sizes[0]}-{sizes[-1]}",
+           "value": perf["f64"]["value"],
+           "unit": "cell-updates/s", "dtype": "f64", "f32": perf["f32"], "f64": perf["f64"], "l1": table}
+    if with_cpu:
+        log("CPU oracle baseline (entropy wave, oblique, 128^2, to t = 1)")
+        out["cpu_baseline"] = cpu_baseline_convergence()
+    return out
+
+
+def cpu_baseline_convergence(n: int = 128):
+    """The FP64 oracle on one problem of the study: the oblique entropy wave
+    on 128^2 cells with analytic boundaries, advanced to t = 1."""
+    import numpy as np
+    import oracle
+    m = oracle.Mesh(2, (n, n), 1.4, (oracle.ANALYTIC, oracle.ANALYTIC))
+    an = oracle.Analytic(oracle.ENTROPY_WAVE, math.pi / 3)
+    U0 = np.ascontiguousarray(oracle.exact_state(m, an, 0.0))
+    t0 = time.perf_counter()
+    _, t, steps = oracle.advance(m, U0, CFL, 1.0, analytic=an)
+    el = time.perf_counter() - t0
+    return {"value": n * n * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oblique entropy wave, {n}x{n}, {steps} FP64 steps to t = 1, serial C, {el:.1f} s"}
 
 
 def main():
@@ -217,8 +292,10 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline FP32 only")
     ap.add_argument("--variant", type=str, default=None, help="JSON variant for the headline run")
     ap.add_argument("--workload", default="kh2048",
-                    choices=("kh2048", "sod1024", "box256", "box512", "batch512"),
+                    choices=("kh2048", "sod1024", "box256", "box512", "batch512", "convergence"),
                     help="kh2048 is the headline; the others print their own line")
+    ap.add_argument("--sizes", type=int, nargs="*", default=None,
+                    help="convergence workload: mesh sizes N (default 16 32 ... 1024)")
     ap.add_argument("--prof", action="store_true",
                     help="profiling run: headline only, plus a 512 MiB device copy that calibrates HBM counters")
     args = ap.parse_args()
@@ -237,7 +314,7 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     if args.workload != "kh2048":
-        out = other_workload(args.workload, args.steps, args.warmup)
+        out = other_workload(args.workload, args.steps, args.warmup, args.sizes, not args.no_cpu)
         out.update({"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "data": "synthetic"})
         if args.prof:
             calibration_copy()

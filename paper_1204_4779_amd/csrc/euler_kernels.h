@@ -621,12 +621,33 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_direct(Args
 constexpr int kMaxR = 8;  // cells per thread kept in registers
 
 // Load U on the region `box` (origin org - H) into LDS primitives.
-// Cells outside the mesh on an analytic axis take the exact solution at
-// their centre and time t_ghost (the time the stage's input stands for).
 template <typename T, int D>
 __device__ __forceinline__ void lds_load_prims(const MeshDev& M, const Fields<T, D>& U, const Box& box,
                                                const int* org, int H, const Gas<T>& g, T* sV,
-                                               int vstride, double t_ghost = 0.0) {
+                                               int vstride) {
+  for (int l = threadIdx.x; l < box.count; l += blockDim.x) {
+    int i, j, k;
+    box.coords(l, i, j, k);
+    const int gi = map_index(org[0] - H + i, M.n[0], M.bc[0]);
+    const int gj = D > 1 ? map_index(org[1] - H + j, M.n[1], M.bc[1]) : 0;
+    const int gk = D > 2 ? map_index(org[2] - H + k, M.n[2], M.bc[2]) : 0;
+    const int gc = gidx(M, gi, gj, gk);
+    T u[D + 2], v[D + 2];
+#pragma unroll
+    for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][gc];
+    prim_of_cons<T, D>(u, v, g);
+#pragma unroll
+    for (int q = 0; q < D + 2; ++q) sV[q * vstride + l] = v[q];
+  }
+}
+
+// Analytic boundaries: after lds_load_prims (which wraps such axes), the
+// cells of the box outside the mesh on an analytic axis take the exact
+// solution at their centres and time t_ghost (the time the stage's input
+// stands for).  Each position is rewritten by the thread that loaded it.
+template <typename T, int D>
+__device__ __forceinline__ void lds_analytic_ghosts(const MeshDev& M, const Box& box, const int* org, int H, T* sV,
+                                                 int vstride, double t_ghost) {
   for (int l = threadIdx.x; l < box.count; l += blockDim.x) {
     int i, j, k;
     box.coords(l, i, j, k);
@@ -634,22 +655,23 @@ __device__ __forceinline__ void lds_load_prims(const MeshDev& M, const Fields<T,
     bool ghost = false;
 #pragma unroll
     for (int a = 0; a < D; ++a) ghost |= M.bc[a] == kAnalytic && (r[a] < 0 || r[a] >= M.n[a]);
-    T v[D + 2];
     if (ghost) {
+      T v[D + 2];
       exact_prims<T, D>(M, (r[0] + 0.5) * M.dx[0], D > 1 ? (r[1] + 0.5) * M.dx[1] : 0.0, t_ghost, v);
-    } else {
-      const int gi = map_index(r[0], M.n[0], M.bc[0]);
-      const int gj = D > 1 ? map_index(r[1], M.n[1], M.bc[1]) : 0;
-      const int gk = D > 2 ? map_index(r[2], M.n[2], M.bc[2]) : 0;
-      const int gc = gidx(M, gi, gj, gk);
-      T u[D + 2];
 #pragma unroll
-      for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][gc];
-      prim_of_cons<T, D>(u, v, g);
+      for (int q = 0; q < D + 2; ++q) sV[q * vstride + l] = v[q];
     }
-#pragma unroll
-    for (int q = 0; q < D + 2; ++q) sV[q * vstride + l] = v[q];
   }
+}
+
+// Does the box reach outside the mesh on an analytic axis?
+template <int D>
+__device__ __forceinline__ bool box_meets_analytic(const MeshDev& M, const Box& box, const int* org, int H) {
+  bool meets = false;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    meets |= M.bc[a] == kAnalytic && (org[a] - H < 0 || org[a] - H + box.e[a] > M.n[a]);
+  return meets;
 }
 
 // Face fluxes along AX for the faces in `faces` (face (i,j,k) lies on the
@@ -714,8 +736,9 @@ __device__ __forceinline__ void lds_all_axes(const LdsGeom& G, const Box& cells,
   }
 }
 
-// Unfused LDS stage: U_out = U0 + cdt L(U_in) on the tile.
-template <typename T, int D, int W>
+// Unfused LDS stage: U_out = U0 + cdt L(U_in) on the tile.  AN: meshes may
+// have analytic boundaries (a separate instantiation keeps the others' code).
+template <typename T, int D, int W, bool AN = false>
 __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a, LdsGeom G) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
@@ -745,10 +768,15 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
 #pragma unroll
       for (int q = 0; q < D + 2; ++q) acc[r][q] = T(0);
     if (active) {
-      // analytic ghosts: stage 1 reads U0 at time t, stage 2 the midpoint state at t + dt/2
-      const double t_ghost = a.ctl[t.m].t[a.ring] + (a.stage == 2 ? 0.5 * dt : 0.0);
       __syncthreads();  // previous item's readers of sV / sF are done
-      lds_load_prims<T, D>(M, Uin, G.vin, t.org, G.halo, g, sV, G.vstride, t_ghost);
+      lds_load_prims<T, D>(M, Uin, G.vin, t.org, G.halo, g, sV, G.vstride);
+      if constexpr (AN) {
+        // stage 1 reads U0 at time t, stage 2 the midpoint state at t + dt/2
+        if (box_meets_analytic<D>(M, G.vin, t.org, G.halo)) {
+          const double t_ghost = a.ctl[t.m].t[a.ring] + (a.stage == 2 ? 0.5 * dt : 0.0);
+          lds_analytic_ghosts<T, D>(M, G.vin, t.org, G.halo, sV, G.vstride, t_ghost);
+        }
+      }
       __syncthreads();
       lds_all_axes<T, D>(G, G.tile, G.fx, G.vin, G.halo, sV, sF, g, coef, acc);
     }

@@ -12,6 +12,8 @@ const KernelTable* table_f32_1() {
   static const KernelTable t = {
       PARAISO_SET(k_stage_direct),
       PARAISO_SET(k_stage_lds),
+      {(const void*)k_stage_lds<float, 1, 0, true>, (const void*)k_stage_lds<float, 1, 3, true>,
+       (const void*)k_stage_lds<float, 1, 4, true>, (const void*)k_stage_lds<float, 1, 5, true>},
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},

@@ -12,6 +12,8 @@ const KernelTable* table_f64_2() {
   static const KernelTable t = {
       PARAISO_SET(k_stage_direct),
       PARAISO_SET(k_stage_lds),
+      {(const void*)k_stage_lds<double, 2, 0, true>, (const void*)k_stage_lds<double, 2, 3, true>,
+       (const void*)k_stage_lds<double, 2, 4, true>, (const void*)k_stage_lds<double, 2, 5, true>},
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
       {(const void*)k_march2d<double, 0, true>, (const void*)k_march2d<double, 3, true>,

@@ -12,6 +12,8 @@ const KernelTable* table_f64_3() {
   static const KernelTable t = {
       PARAISO_SET(k_stage_direct),
       PARAISO_SET(k_stage_lds),
+      {(const void*)k_stage_lds<double, 3, 0, true>, (const void*)k_stage_lds<double, 3, 3, true>,
+       (const void*)k_stage_lds<double, 3, 4, true>, (const void*)k_stage_lds<double, 3, 5, true>},
       PARAISO_SET(k_fused_lds),
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},

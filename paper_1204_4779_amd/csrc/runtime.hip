@@ -516,6 +516,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   else if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
   else if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
   else if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
+  else if (v.lds && any_analytic(c->meshes.data(), c->count)) L.fn = c->tab->stage_lds_analytic[ws];
   else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
   if (!L.fn) return fail(PARAISO_ERR_UNSUPPORTED, "variant: no kernel for this combination");
   L.block = dim3(threads);
