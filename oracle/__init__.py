@@ -58,7 +58,7 @@ def build(force: bool = True) -> str:
 
 
 class _Mesh(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    _fields_ = [("ndim", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("n", ctypes.c_int64 * 3), ("dx", ctypes.c_double * 3),
                 ("gamma", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
                 ("pad2_", ctypes.c_int32)]
@@ -134,6 +134,7 @@ class Mesh:
     gamma: float
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
     dx: tuple | None = None
+    order: int = 2      # reconstruction: 2 minbee piecewise linear, 1 piecewise constant
     _c: _Mesh = field(init=False, repr=False)
 
     def __post_init__(self):
@@ -147,6 +148,7 @@ class Mesh:
         self.bc = bc
         c = _Mesh()
         c.ndim = self.ndim
+        c.order = int(self.order)
         for a in range(3):
             c.n[a] = n[a]
             c.dx[a] = self.dx[a]

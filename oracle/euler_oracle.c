@@ -14,7 +14,9 @@
  *     the sign printed in the paper is read as the usual one, which is the
  *     one its AddFlux update implements);
  *   - piecewise-linear reconstruction of every primitive, axis by axis, with
- *     the minbee (minmod) limiter (Interpolate equation);
+ *     the minbee (minmod) limiter (Interpolate equation); or, as the order-1
+ *     branch of the paper's interpolation listing, piecewise constant: the
+ *     face takes the values of the two cells beside it;
  *   - the HLLC approximate Riemann flux of Toro, Spruce and Speares (1994),
  *     which the paper cites but does not print: Davis wave-speed estimates
  *     and the conserved star state (reading stated in the design notes);
@@ -78,7 +80,7 @@ typedef struct {
 
 typedef struct {
   int32_t ndim;
-  int32_t pad_;
+  int32_t order; /* reconstruction: 2 piecewise linear with minbee (default), 1 piecewise constant */
   int64_t n[3];
   double dx[3];
   double gamma;
@@ -89,6 +91,7 @@ typedef struct {
 static int check_mesh(const orc_mesh* m) {
   if (!m) return ORC_BAD_ARG;
   if (m->ndim < 1 || m->ndim > 3) return ORC_BAD_ARG;
+  if (m->order != 1 && m->order != 2) return ORC_BAD_ARG;
   if (!(m->gamma > 1.0) || !isfinite(m->gamma)) return ORC_BAD_ARG;
   for (int a = 0; a < 3; ++a) {
     if (m->n[a] < 1) return ORC_BAD_ARG;
@@ -512,6 +515,12 @@ int orc_stage_t(const orc_mesh* m, const orc_analytic* an, double t, const doubl
           double vl[5], vr[5];
           for (int q = 0; q < nf; ++q) {
             const double* y = P.v + q * P.np;
+            if (m->order == 1) {
+              /* piecewise constant: the two cells' own values */
+              vl[q] = y[c - stride];
+              vr[q] = y[c];
+              continue;
+            }
             double lo, hi;
             /* left cell (c - stride): its upper-face value */
             orc_interpolate(y[c - 2 * stride], y[c - stride], y[c], &lo, &hi);

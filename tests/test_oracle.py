@@ -506,3 +506,91 @@ def test_convergence_with_analytic_boundaries(kind, angle):
     errs = [_l1_rho(_unit_square(n), an, 1.0) for n in (32, 64, 128)]
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert all(o > 1.6 for o in orders), (errs, orders)
+
+
+# ---- first-order reconstruction: the order-1 branch of the interpolation ------------
+
+def test_first_order_stage_is_the_godunov_update():
+    # order 1: each face sees the two cells beside it, so one stage is the
+    # three-point update U_i - c (F(V_i, V_i+1) - F(V_i-1, V_i)) with the
+    # (separately pinned) HLLC flux; written here cell by cell
+    pr = inputs.random_state(1, (23,), seed=71, rough=True, bc=(1,))
+    m = oracle.Mesh(1, pr.n, pr.gamma, pr.bc, order=1)
+    V = np.array([oracle.prim_of_cons(1, pr.gamma, pr.U[:, i]) for i in range(23)])
+    cdt = 2e-3
+    want = np.empty_like(pr.U)
+    for i in range(23):
+        lo, hi = V[max(i - 1, 0)], V[min(i + 1, 22)]       # outflow: edge cell copied
+        f_minus = oracle.hllc(1, pr.gamma, 0, lo, V[i])
+        f_plus = oracle.hllc(1, pr.gamma, 0, V[i], hi)
+        want[:, i] = pr.U[:, i] - cdt / m.dx[0] * (f_plus - f_minus)
+    got = oracle.stage(m, pr.U, pr.U, cdt)
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-14 * np.max(np.abs(want)))
+
+
+@pytest.mark.parametrize("order,reach", [(1, 2), (2, 4)])
+def test_stencil_reach_of_a_step(order, reach):
+    # a step is two stages of a stencil one face wide (order 1) or two
+    # faces wide (order 2): cell 20 of a periodic 1D mesh depends on cells
+    # 20 +- reach and on no cell further away
+    # The limiter keeps the smaller one-sided difference and so can hide a
+    # cell inside the reach; on a convex increasing profile every slope is
+    # the left difference, which exposes the far left cell.
+    m = oracle.Mesh(1, (41,), 1.4, (1,), order=order)
+    U0 = np.array([oracle.cons_of_prim(1, 1.4, [1.0 + 1e-3 * i * i, 0.1, 1.0 + 2e-3 * i * i])
+                   for i in range(41)]).T.copy()
+    base = oracle.step(m, U0, 1e-3)[:, 20]
+    seen = set()
+    for dist in range(1, 8):
+        for side in (-1, 1):
+            U = U0.copy()
+            U[0, 20 + side * dist] *= 1.1
+            U[2, 20 + side * dist] *= 1.2
+            if np.any(oracle.step(m, U, 1e-3)[:, 20] != base):
+                seen.add(dist)
+    assert max(seen) == reach and {1, 2} <= seen, (order, seen)
+
+
+def test_first_order_keeps_uniform_flow_and_symmetry():
+    pr = inputs.uniform_flow(2, (12, 7), bc=(1, 0))
+    m = oracle.Mesh(2, pr.n, pr.gamma, pr.bc, order=1)
+    np.testing.assert_array_equal(oracle.step(m, pr.U, 3e-3), pr.U)
+    pr = inputs.random_state(1, (40,), seed=73, rough=True, bc=(1,))
+    m = oracle.Mesh(1, pr.n, pr.gamma, pr.bc, order=1)
+    mirror = pr.U[:, ::-1].copy()
+    mirror[1] *= -1.0
+    a = oracle.step(m, pr.U, 2e-3)
+    b = oracle.step(m, mirror, 2e-3)[:, ::-1].copy()
+    b[1] *= -1.0
+    np.testing.assert_allclose(b, a, rtol=1e-13, atol=1e-13 * np.max(np.abs(a)))
+
+
+def test_first_order_converges_at_first_order():
+    # entropy wave on the unit square (analytic boundaries) to t = 1: the
+    # first-order scheme's L1 error halves with the cell size (order ~1),
+    # the minbee scheme's falls at ~2 and is smaller at every N
+    an = oracle.Analytic(oracle.ENTROPY_WAVE, 0.0)
+    e1, e2 = [], []
+    for n in (16, 32, 64):
+        for order, errs in ((1, e1), (2, e2)):
+            m = oracle.Mesh(2, (n, 4), 1.4, (oracle.ANALYTIC, oracle.PERIODIC), order=order)
+            U, t, _ = oracle.advance(m, oracle.exact_state(m, an, 0.0), 0.5, 1.0, analytic=an)
+            errs.append(float(np.mean(np.abs(U[0] - oracle.exact_state(m, an, 1.0)[0]))))
+    o1 = [math.log2(e1[i] / e1[i + 1]) for i in range(2)]
+    assert all(0.75 < o < 1.15 for o in o1), (e1, o1)
+    assert all(a > 2 * b for a, b in zip(e1, e2)), (e1, e2)
+
+
+def test_first_order_sod_against_exact():
+    # Sod 1D, 512 cells, to t = 0.2: the piecewise-constant scheme smears
+    # more than minbee but converges to the exact solution
+    x = inputs.centres(512)
+    ex = er.sample_cells(1.4, er.Side(1, 0, 1), er.Side(0.125, 0, 0.1), 0.5, 0.2, x)
+    rho_ex = np.array([e[0] for e in ex])
+    errs = {}
+    for order in (1, 2):
+        pr = inputs.sod_1d(512)
+        m = oracle.Mesh(1, pr.n, pr.gamma, pr.bc, order=order)
+        U, t, _ = oracle.advance(m, pr.U, 0.5, 0.2)
+        errs[order] = float(np.mean(np.abs(U[0] - rho_ex)))
+    assert errs[2] < errs[1] < 1e-2, errs
