@@ -72,6 +72,11 @@ extern "C" {
  * device pointer; the two buffers must not overlap.  The library reads the
  * current state from one buffer and writes the next state to the other
  * (paraiso_current says which holds the current state).
+ * order selects the reconstruction of the Interpolate equation: 2 (or 0)
+ * piecewise linear with the minbee limiter, 1 piecewise constant (each face
+ * takes the values of the two cells beside it: the order-1 branch of the
+ * paper's interpolation listing, section "Annotating By Hand"; runs on the
+ * LDS-tile kernels, and all meshes of a batch share it).
  * Limits: n[0]*n[1]*n[2] < 2^31.
  */
 typedef struct paraiso_mesh {
@@ -81,7 +86,7 @@ typedef struct paraiso_mesh {
   double dx[3];
   double gamma;
   int32_t bc[3];
-  int32_t reserved;
+  int32_t order;
   void* state[2][5];
 } paraiso_mesh;
 
@@ -143,8 +148,8 @@ int32_t paraiso_workspace_bytes(const paraiso_mesh* meshes, int32_t count, size_
  * hipStream_t (NULL = the default stream).  The mesh descriptors are copied;
  * buffer 0 holds the initial state.
  * Errors: INVALID_ARG (null pointers, ndim not in 1..3, n < 1, gamma <= 1,
- * dx <= 0 or non-finite, bc not PERIODIC/OUTFLOW/ANALYTIC, overlapping buffers,
- * mixed ndim/dtype in a batch), UNSUPPORTED (too many cells),
+ * dx <= 0 or non-finite, bc not PERIODIC/OUTFLOW/ANALYTIC, order not 0/1/2,
+ * overlapping buffers, mixed ndim/dtype/order in a batch), UNSUPPORTED (too many cells),
  * WORKSPACE (workspace too small), HIP.
  */
 int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
@@ -159,7 +164,7 @@ int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
  * paraiso_init): 1D the resident kernel when every mesh fits one
  * workgroup, else LDS tiles; 2D the fused register march when every mesh is
  * periodic on both axes, else LDS tiles; 3D the register march.  Any mesh
- * with an analytic axis: unfused LDS tiles. */
+ * with an analytic axis: unfused LDS tiles; first order: LDS tiles. */
 int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
 
 /*

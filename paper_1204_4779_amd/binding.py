@@ -52,7 +52,7 @@ class NonFiniteError(ParaisoError, FloatingPointError):
 class paraiso_mesh(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n", ctypes.c_int64 * 3),
                 ("dx", ctypes.c_double * 3), ("gamma", ctypes.c_double), ("bc", ctypes.c_int32 * 3),
-                ("reserved", ctypes.c_int32), ("state", (ctypes.c_void_p * 5) * 2)]
+                ("order", ctypes.c_int32), ("state", (ctypes.c_void_p * 5) * 2)]
 
 
 class paraiso_analytic(ctypes.Structure):
@@ -268,6 +268,7 @@ class MeshSpec:
     gamma: float
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
     dx: tuple | None = None
+    order: int = 2        # reconstruction: 2 minbee piecewise linear, 1 piecewise constant
 
     def n3(self):
         return tuple(int(v) for v in self.n) + (1,) * (3 - len(self.n))
@@ -319,6 +320,7 @@ class Solver:
                 m.dx[a] = dx[a]
                 m.bc[a] = bc[a]
             m.gamma = float(sp.gamma)
+            m.order = int(sp.order)
             for b, buf in enumerate((b0, b1)):
                 for q in range(self.nf):
                     m.state[b][q] = buf[q].data_ptr()   # field q: contiguous, 256-byte aligned

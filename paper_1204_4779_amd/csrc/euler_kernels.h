@@ -674,10 +674,15 @@ __device__ __forceinline__ bool box_meets_analytic(const MeshDev& M, const Box& 
   return meets;
 }
 
+// Options of the LDS-tile kernels, one instantiation each (bit mask).
+constexpr int kOptAnalytic = 1;    // exact-solution ghosts on analytic axes
+constexpr int kOptFirstOrder = 2;  // piecewise-constant reconstruction
+
 // Face fluxes along AX for the faces in `faces` (face (i,j,k) lies on the
 // lower side of cell (i,j,k) of the cell box that starts `off` cells into
-// the V region).  Reads sV, writes sF.
-template <typename T, int D, int AX>
+// the V region).  Reads sV, writes sF.  FIRST: the face takes the values of
+// the two cells beside it (first-order reconstruction).
+template <typename T, int D, int AX, bool FIRST = false>
 __device__ __forceinline__ void lds_fluxes(const Box& faces, const Box& vbox, int off, const T* sV,
                                            int vstride, T* sF, int fstride, const Gas<T>& g) {
   const int s = AX == 0 ? 1 : (AX == 1 ? vbox.e[0] : vbox.e[0] * vbox.e[1]);
@@ -689,7 +694,12 @@ __device__ __forceinline__ void lds_fluxes(const Box& faces, const Box& vbox, in
 #pragma unroll
     for (int q = 0; q < D + 2; ++q) {
       const T* y = sV + q * vstride + c;
-      face_states(y[-2 * s], y[-s], y[0], y[s], vl[q], vr[q]);
+      if constexpr (FIRST) {
+        vl[q] = y[-s];
+        vr[q] = y[0];
+      } else {
+        face_states(y[-2 * s], y[-s], y[0], y[s], vl[q], vr[q]);
+      }
     }
     hllc<T, D, AX>(vl, vr, f, g);
 #pragma unroll
@@ -715,31 +725,34 @@ __device__ __forceinline__ void lds_accumulate(const Box& cells, const Box& face
   }
 }
 
-template <typename T, int D>
+template <typename T, int D, bool FIRST = false>
 __device__ __forceinline__ void lds_all_axes(const LdsGeom& G, const Box& cells, const Box* faces,
                                              const Box& vbox, int off, const T* sV, T* sF,
                                              const Gas<T>& g, const T* coef, T (*acc)[D + 2]) {
-  lds_fluxes<T, D, 0>(faces[0], vbox, off, sV, G.vstride, sF, G.fstride, g);
+  lds_fluxes<T, D, 0, FIRST>(faces[0], vbox, off, sV, G.vstride, sF, G.fstride, g);
   __syncthreads();
   lds_accumulate<T, D, 0>(cells, faces[0], sF, G.fstride, coef[0], acc);
   if constexpr (D > 1) {
     __syncthreads();
-    lds_fluxes<T, D, 1>(faces[1], vbox, off, sV, G.vstride, sF, G.fstride, g);
+    lds_fluxes<T, D, 1, FIRST>(faces[1], vbox, off, sV, G.vstride, sF, G.fstride, g);
     __syncthreads();
     lds_accumulate<T, D, 1>(cells, faces[1], sF, G.fstride, coef[1], acc);
   }
   if constexpr (D > 2) {
     __syncthreads();
-    lds_fluxes<T, D, 2>(faces[2], vbox, off, sV, G.vstride, sF, G.fstride, g);
+    lds_fluxes<T, D, 2, FIRST>(faces[2], vbox, off, sV, G.vstride, sF, G.fstride, g);
     __syncthreads();
     lds_accumulate<T, D, 2>(cells, faces[2], sF, G.fstride, coef[2], acc);
   }
 }
 
-// Unfused LDS stage: U_out = U0 + cdt L(U_in) on the tile.  AN: meshes may
-// have analytic boundaries (a separate instantiation keeps the others' code).
-template <typename T, int D, int W, bool AN = false>
+// Unfused LDS stage: U_out = U0 + cdt L(U_in) on the tile.  OPT (kOpt*
+// bits): analytic ghosts, first-order reconstruction; separate
+// instantiations keep the plain kernel's code and registers.
+template <typename T, int D, int W, int OPT = 0>
 __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a, LdsGeom G) {
+  constexpr bool AN = (OPT & kOptAnalytic) != 0;
+  constexpr bool FIRST = (OPT & kOptFirstOrder) != 0;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
   __shared__ int s_item;
@@ -778,7 +791,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
         }
       }
       __syncthreads();
-      lds_all_axes<T, D>(G, G.tile, G.fx, G.vin, G.halo, sV, sF, g, coef, acc);
+      lds_all_axes<T, D, FIRST>(G, G.tile, G.fx, G.vin, G.halo, sV, sF, g, coef, acc);
     }
     double qmax = 0.0;
     bool bad = false;
@@ -812,8 +825,11 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
 // Fused LDS step: V0 on tile+4 -> stage 1 on tile+2 (kept in LDS) -> stage 2
 // on the tile.  Outflow: stage-1 values outside the mesh are replaced by the
 // edge cell's stage-1 value, which is what filling ghost cells of U1 does.
-template <typename T, int D, int W>
+// OPT: kOptFirstOrder or 0 (analytic boundaries need the unfused kernel).
+template <typename T, int D, int W, int OPT = 0>
 __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_lds(Args a, LdsGeom G) {
+  constexpr bool FIRST = (OPT & kOptFirstOrder) != 0;
+  static_assert((OPT & kOptAnalytic) == 0, "analytic ghosts run on the unfused kernel");
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
   __shared__ int s_item;
@@ -845,7 +861,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_lds(Args a,
       __syncthreads();
       lds_load_prims<T, D>(M, U0, G.vin, t.org, 4, g, sV, G.vstride);
       __syncthreads();
-      lds_all_axes<T, D>(G, G.c1, G.fx, G.vin, 2, sV, sF, g, coef1, acc);
+      lds_all_axes<T, D, FIRST>(G, G.c1, G.fx, G.vin, 2, sV, sF, g, coef1, acc);
       __syncthreads();  // all stage-1 readers of V0 done: sV now holds V1 on tile + 2
 #pragma unroll
       for (int r = 0; r < kMaxR; ++r) {
@@ -903,7 +919,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_lds(Args a,
       for (int r = 0; r < kMaxR; ++r)
 #pragma unroll
         for (int q = 0; q < D + 2; ++q) acc[r][q] = T(0);
-      lds_all_axes<T, D>(G, G.tile, G.fx2, G.c1, 2, sV, sF, g, coef2, acc);
+      lds_all_axes<T, D, FIRST>(G, G.tile, G.fx2, G.c1, 2, sV, sF, g, coef2, acc);
     }
     double qmax = 0.0;
     bool bad = false;

@@ -7,14 +7,16 @@ namespace paraiso {
 
 #define PARAISO_SET(K) {(const void*)K<float, 2, 0>, (const void*)K<float, 2, 3>, \
                         (const void*)K<float, 2, 4>, (const void*)K<float, 2, 5>}
+#define PARAISO_SET_OPT(K, O) {(const void*)K<float, 2, 0, O>, (const void*)K<float, 2, 3, O>, \
+                               (const void*)K<float, 2, 4, O>, (const void*)K<float, 2, 5, O>}
 
 const KernelTable* table_f32_2() {
   static const KernelTable t = {
       PARAISO_SET(k_stage_direct),
       PARAISO_SET(k_stage_lds),
-      {(const void*)k_stage_lds<float, 2, 0, true>, (const void*)k_stage_lds<float, 2, 3, true>,
-       (const void*)k_stage_lds<float, 2, 4, true>, (const void*)k_stage_lds<float, 2, 5, true>},
+      {PARAISO_SET_OPT(k_stage_lds, 1), PARAISO_SET_OPT(k_stage_lds, 2), PARAISO_SET_OPT(k_stage_lds, 3)},
       PARAISO_SET(k_fused_lds),
+      PARAISO_SET_OPT(k_fused_lds, 2),
       PARAISO_SET(k_fused_direct),
       {(const void*)k_march2d<float, 0, true>, (const void*)k_march2d<float, 3, true>,
        (const void*)k_march2d<float, 4, true>, (const void*)k_march2d<float, 5, true>},

@@ -7,14 +7,16 @@ namespace paraiso {
 
 #define PARAISO_SET(K) {(const void*)K<double, 1, 0>, (const void*)K<double, 1, 3>, \
                         (const void*)K<double, 1, 4>, (const void*)K<double, 1, 5>}
+#define PARAISO_SET_OPT(K, O) {(const void*)K<double, 1, 0, O>, (const void*)K<double, 1, 3, O>, \
+                               (const void*)K<double, 1, 4, O>, (const void*)K<double, 1, 5, O>}
 
 const KernelTable* table_f64_1() {
   static const KernelTable t = {
       PARAISO_SET(k_stage_direct),
       PARAISO_SET(k_stage_lds),
-      {(const void*)k_stage_lds<double, 1, 0, true>, (const void*)k_stage_lds<double, 1, 3, true>,
-       (const void*)k_stage_lds<double, 1, 4, true>, (const void*)k_stage_lds<double, 1, 5, true>},
+      {PARAISO_SET_OPT(k_stage_lds, 1), PARAISO_SET_OPT(k_stage_lds, 2), PARAISO_SET_OPT(k_stage_lds, 3)},
       PARAISO_SET(k_fused_lds),
+      PARAISO_SET_OPT(k_fused_lds, 2),
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},

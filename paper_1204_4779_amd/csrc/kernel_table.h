@@ -9,8 +9,9 @@ inline int waves_slot(int w) { return w == 3 ? 1 : (w == 4 ? 2 : (w == 5 ? 3 : 0
 struct KernelTable {
   const void* stage_direct[4];
   const void* stage_lds[4];
-  const void* stage_lds_analytic[4];  // the same with exact-solution ghosts on analytic axes
+  const void* stage_lds_opt[3][4];  // [kOpt* bits - 1]: analytic ghosts, first order, both
   const void* fused_lds[4];
+  const void* fused_lds_first[4];  // first-order reconstruction
   const void* fused_direct[4];
   const void* march_fused[4];  // 2D register march (null for other dimensions)
   const void* march_stage[4];

@@ -62,6 +62,8 @@ bool has_analytic(const paraiso_mesh& m) {
   return false;
 }
 
+bool first_order(const paraiso_mesh& m) { return m.order == 1; }
+
 bool any_analytic(const paraiso_mesh* ms, int count) {
   for (int i = 0; i < count; ++i)
     if (has_analytic(ms[i])) return true;
@@ -116,6 +118,8 @@ int validate_mesh(const paraiso_mesh& m, int idx) {
     return fail(PARAISO_ERR_INVALID_ARG, w + "dtype must be PARAISO_F32 or PARAISO_F64");
   if (!(m.gamma > 1.0) || !std::isfinite(m.gamma))
     return fail(PARAISO_ERR_INVALID_ARG, w + "gamma must be finite and > 1");
+  if (m.order != 0 && m.order != 1 && m.order != 2)
+    return fail(PARAISO_ERR_INVALID_ARG, w + "order must be 0 (= 2), 1 or 2");
   for (int a = 0; a < 3; ++a) {
     if (m.n[a] < 1) return fail(PARAISO_ERR_INVALID_ARG, w + "n[a] must be >= 1");
     if (a >= m.ndim) {
@@ -155,6 +159,8 @@ int validate_meshes(const paraiso_mesh* ms, int count) {
     if (rc) return rc;
     if (ms[i].ndim != ms[0].ndim || ms[i].dtype != ms[0].dtype)
       return fail(PARAISO_ERR_INVALID_ARG, "all meshes of a batch must share ndim and dtype");
+    if (first_order(ms[i]) != first_order(ms[0]))
+      return fail(PARAISO_ERR_INVALID_ARG, "all meshes of a batch must share the reconstruction order");
   }
   return PARAISO_OK;
 }
@@ -411,6 +417,8 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   if (any_analytic(c->meshes.data(), c->count) && (v.lds != 1 || v.fuse != 0))
     return why = "analytic boundaries run on the unfused LDS-tile kernel (lds = 1, fuse = 0)",
            PARAISO_ERR_UNSUPPORTED;
+  if (first_order(c->meshes[0]) && v.lds != 1)
+    return why = "first-order reconstruction runs on the LDS-tile kernels (lds = 1)", PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
@@ -515,9 +523,13 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   if (v.lds == 3) L.fn = c->tab->resident1d;
   else if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
   else if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
-  else if (v.fuse) L.fn = v.lds ? c->tab->fused_lds[ws] : c->tab->fused_direct[ws];
-  else if (v.lds && any_analytic(c->meshes.data(), c->count)) L.fn = c->tab->stage_lds_analytic[ws];
-  else L.fn = v.lds ? c->tab->stage_lds[ws] : c->tab->stage_direct[ws];
+  else if (v.lds == 1) {
+    const int opt = (any_analytic(c->meshes.data(), c->count) ? kOptAnalytic : 0) |
+                    (first_order(c->meshes[0]) ? kOptFirstOrder : 0);
+    if (v.fuse) L.fn = opt ? c->tab->fused_lds_first[ws] : c->tab->fused_lds[ws];
+    else L.fn = opt ? c->tab->stage_lds_opt[opt - 1][ws] : c->tab->stage_lds[ws];
+  } else if (v.fuse) L.fn = c->tab->fused_direct[ws];
+  else L.fn = c->tab->stage_direct[ws];
   if (!L.fn) return fail(PARAISO_ERR_UNSUPPORTED, "variant: no kernel for this combination");
   L.block = dim3(threads);
   L.shmem = shmem;
@@ -600,6 +612,8 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
   lds_variant(d, v);
   if (any_analytic(meshes, count)) {
     v->fuse = 0;  // ghosts at each stage's own time
+  } else if (first_order(meshes[0])) {
+    // first-order reconstruction: the LDS-tile kernels only
   } else if (d == 1) {
     int64_t nmax = 1;
     for (int m = 0; m < count; ++m) nmax = std::max<int64_t>(nmax, meshes[m].n[0]);

@@ -34,9 +34,9 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
-def _mesh(ndim=2, n=(8, 8, 1), dtype=pb.F32, gamma=1.4, bc=(0, 0, 0), base=0x10000, dx=None):
+def _mesh(ndim=2, n=(8, 8, 1), dtype=pb.F32, gamma=1.4, bc=(0, 0, 0), base=0x10000, dx=None, order=0):
     m = pb.paraiso_mesh()
-    m.ndim, m.dtype, m.gamma = ndim, dtype, gamma
+    m.ndim, m.dtype, m.gamma, m.order = ndim, dtype, gamma, order
     for a in range(3):
         m.n[a] = n[a]
         m.dx[a] = (dx[a] if dx else 1.0 / max(n[a], 1))
@@ -59,7 +59,7 @@ def test_workspace_bytes_valid(lib):
 @pytest.mark.parametrize("bad", [
     dict(ndim=0), dict(ndim=4), dict(gamma=1.0), dict(gamma=float("nan")), dict(n=(0, 8, 1)),
     dict(ndim=2, n=(8, 8, 2)), dict(bc=(3, 0, 0)), dict(bc=(0, -1, 0)), dict(dtype=7), dict(dx=(0.0, 1.0, 1.0)),
-    dict(dx=(float("inf"), 1.0, 1.0)),
+    dict(dx=(float("inf"), 1.0, 1.0)), dict(order=3), dict(order=-1),
 ])
 def test_workspace_bytes_rejects_invalid_mesh(lib, bad):
     with pytest.raises(pb.ParaisoError) as ei:
@@ -134,6 +134,21 @@ def test_default_variant(lib):
         assert (v.lds, v.fuse) == (1, 0), d
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, pb.ANALYTIC, 0))])
     assert (v.lds, v.fuse, v.persistent) == (1, 0, 1)
+    # first-order reconstruction: the LDS-tile kernels (fused unless analytic)
+    for d, n in ((1, (64, 1, 1)), (2, (8, 8, 1)), (3, (4, 4, 4))):
+        v = pb.paraiso_default_variant([_mesh(d, n, order=1)])
+        assert v.lds == 1 and v.fuse == (0 if d == 3 else 1), d
+        v = pb.paraiso_default_variant([_mesh(d, n, order=1, bc=(pb.ANALYTIC, 0, 0))])
+        assert (v.lds, v.fuse) == (1, 0), d
+    assert pb.paraiso_default_variant([_mesh(order=2)]).lds == 2
+
+
+def test_batch_must_share_the_reconstruction_order(lib):
+    pb.paraiso_workspace_bytes([_mesh(order=1), _mesh(order=1, base=0x8000000)])
+    pb.paraiso_workspace_bytes([_mesh(order=0), _mesh(order=2, base=0x8000000)])
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_workspace_bytes([_mesh(order=1), _mesh(order=2, base=0x8000000)])
+    assert ei.value.code == pb.ERR_INVALID_ARG
 
 
 def test_version(lib):
