@@ -118,7 +118,18 @@ typedef struct paraiso_mesh {
  *                minimum waves per SIMD the kernel is compiled for, which
  *                caps registers per lane at 168, 128 or 100;
  *   threads      workgroup size, a multiple of 64 in [64, 512], or 0 for
- *                the default of the chosen kernel.
+ *                the default of the chosen kernel;
+ *   manifest     what an LDS tile (lds = 1) keeps between the phases of an
+ *                axis, the paper's Manifest/Delayed choice for the results
+ *                of the interpolation and of the Riemann solver (section
+ *                "Annotating By Hand"):
+ *                0: face fluxes, each face's states formed where its flux is
+ *                   computed (interpolation delayed, Riemann manifest);
+ *                1: face states; each cell solves both of its faces
+ *                   (interpolation manifest, Riemann delayed);
+ *                2: face states, then face fluxes (both manifest).
+ *                lds = 0 delays both.  Nonzero only with lds = 1 on
+ *                second-order meshes without analytic boundaries.
  */
 typedef struct paraiso_variant {
   int32_t tile[3];
@@ -127,6 +138,7 @@ typedef struct paraiso_variant {
   int32_t waves_per_eu;
   int32_t threads;
   int32_t persistent;  /* 1: grid of a few workgroups per CU pulling tiles from a queue */
+  int32_t manifest;
 } paraiso_variant;
 
 typedef struct paraiso_ctx paraiso_ctx;

@@ -69,21 +69,21 @@ class paraiso_analytic(ctypes.Structure):
 class paraiso_variant(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32 * 3), ("lds", ctypes.c_int32), ("fuse", ctypes.c_int32),
                 ("waves_per_eu", ctypes.c_int32), ("threads", ctypes.c_int32),
-                ("persistent", ctypes.c_int32)]
+                ("persistent", ctypes.c_int32), ("manifest", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"tile": tuple(self.tile), "lds": self.lds, "fuse": self.fuse,
                 "waves_per_eu": self.waves_per_eu, "threads": self.threads,
-                "persistent": self.persistent}
+                "persistent": self.persistent, "manifest": self.manifest}
 
     @classmethod
-    def make(cls, tile=(32, 16, 1), lds=1, fuse=1, waves_per_eu=0, threads=0, persistent=0):
+    def make(cls, tile=(32, 16, 1), lds=1, fuse=1, waves_per_eu=0, threads=0, persistent=0, manifest=0):
         v = cls()
         t = tuple(tile) + (1,) * (3 - len(tile))
         for a in range(3):
             v.tile[a] = int(t[a])
         v.lds, v.fuse, v.waves_per_eu = int(lds), int(fuse), int(waves_per_eu)
-        v.threads, v.persistent = int(threads), int(persistent)
+        v.threads, v.persistent, v.manifest = int(threads), int(persistent), int(manifest)
         return v
 
 

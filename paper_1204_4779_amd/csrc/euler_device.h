@@ -58,6 +58,18 @@ struct Box {
   }
 };
 
+// A box built on the device (two integer divisions, once per call).
+__device__ __forceinline__ Box make_box_dev(int e0, int e1, int e2) {
+  Box b;
+  b.e[0] = e0;
+  b.e[1] = e1;
+  b.e[2] = e2;
+  b.count = e0 * e1 * e2;
+  b.d0 = FastDiv::make((uint32_t)e0);
+  b.d01 = FastDiv::make((uint32_t)(e0 * e1));
+  return b;
+}
+
 // Map any cell index onto [0, n) along one axis: clamp (outflow) or wrap
 // (periodic).  One add or subtract covers -n <= p < 2n; anything further out
 // (tiles wider than the mesh) takes the remainder.

@@ -17,7 +17,7 @@
 // y-face fluxes from this push and the previous one).
 #pragma once
 
-#include "euler_kernels.h"
+#include "euler_common.h"
 
 namespace paraiso {
 

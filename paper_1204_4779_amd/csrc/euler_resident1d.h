@@ -14,7 +14,7 @@
 // as one buffer flip; t and the step count go to ring slot (ring + 1) % 3.
 #pragma once
 
-#include "euler_kernels.h"
+#include "euler_common.h"
 
 namespace paraiso {
 

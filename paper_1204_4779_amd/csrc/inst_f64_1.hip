@@ -9,6 +9,8 @@ namespace paraiso {
                         (const void*)K<double, 1, 4>, (const void*)K<double, 1, 5>}
 #define PARAISO_SET_OPT(K, O) {(const void*)K<double, 1, 0, O>, (const void*)K<double, 1, 3, O>, \
                                (const void*)K<double, 1, 4, O>, (const void*)K<double, 1, 5, O>}
+#define PARAISO_SET_KEEP(K, KP) {(const void*)K<double, 1, 0, 0, KP>, (const void*)K<double, 1, 3, 0, KP>, \
+                                 (const void*)K<double, 1, 4, 0, KP>, (const void*)K<double, 1, 5, 0, KP>}
 
 const KernelTable* table_f64_1() {
   static const KernelTable t = {
@@ -17,6 +19,8 @@ const KernelTable* table_f64_1() {
       {PARAISO_SET_OPT(k_stage_lds, 1), PARAISO_SET_OPT(k_stage_lds, 2), PARAISO_SET_OPT(k_stage_lds, 3)},
       PARAISO_SET(k_fused_lds),
       PARAISO_SET_OPT(k_fused_lds, 2),
+      {PARAISO_SET_KEEP(k_stage_lds, 1), PARAISO_SET_KEEP(k_stage_lds, 2)},
+      {PARAISO_SET_KEEP(k_fused_lds, 1), PARAISO_SET_KEEP(k_fused_lds, 2)},
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},

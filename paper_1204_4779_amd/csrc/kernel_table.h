@@ -12,6 +12,8 @@ struct KernelTable {
   const void* stage_lds_opt[3][4];  // [kOpt* bits - 1]: analytic ghosts, first order, both
   const void* fused_lds[4];
   const void* fused_lds_first[4];  // first-order reconstruction
+  const void* stage_lds_keep[2][4];  // [manifest - 1]: face states kept in LDS, without / with face fluxes
+  const void* fused_lds_keep[2][4];
   const void* fused_direct[4];
   const void* march_fused[4];  // 2D register march (null for other dimensions)
   const void* march_stage[4];

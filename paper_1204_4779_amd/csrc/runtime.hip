@@ -419,6 +419,11 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
            PARAISO_ERR_UNSUPPORTED;
   if (first_order(c->meshes[0]) && v.lds != 1)
     return why = "first-order reconstruction runs on the LDS-tile kernels (lds = 1)", PARAISO_ERR_UNSUPPORTED;
+  if (v.manifest < 0 || v.manifest > 2) return why = "manifest must be 0, 1 or 2", PARAISO_ERR_UNSUPPORTED;
+  if (v.manifest != 0 && v.lds != 1)
+    return why = "manifest 1 and 2 are choices of the LDS-tile kernels (lds = 1)", PARAISO_ERR_UNSUPPORTED;
+  if (v.manifest != 0 && (any_analytic(c->meshes.data(), c->count) || first_order(c->meshes[0])))
+    return why = "kept face states: second-order meshes without analytic boundaries", PARAISO_ERR_UNSUPPORTED;
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
@@ -507,7 +512,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
       return fail(PARAISO_ERR_UNSUPPORTED, "variant: 3D march needs " + std::to_string(shmem) + " bytes of LDS");
   }
   if (v.lds == 1) {
-    shmem = (size_t)c->esize * nf * ((size_t)G.vstride + G.fstride);
+    // primitives, one axis' face fluxes and, when kept, the face values (lower and upper) of that axis
+    shmem = (size_t)c->esize * nf * ((size_t)G.vstride + G.fstride + (v.manifest ? 2 * (size_t)G.vstride : 0));
     const size_t static_lds = 16 * sizeof(double) + 64;
     if (shmem + static_lds > (size_t)c->max_lds)
       return fail(PARAISO_ERR_UNSUPPORTED, "variant: LDS tile needs " + std::to_string(shmem) + " bytes, limit " +
@@ -526,7 +532,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   else if (v.lds == 1) {
     const int opt = (any_analytic(c->meshes.data(), c->count) ? kOptAnalytic : 0) |
                     (first_order(c->meshes[0]) ? kOptFirstOrder : 0);
-    if (v.fuse) L.fn = opt ? c->tab->fused_lds_first[ws] : c->tab->fused_lds[ws];
+    if (v.manifest) L.fn = v.fuse ? c->tab->fused_lds_keep[v.manifest - 1][ws] : c->tab->stage_lds_keep[v.manifest - 1][ws];
+    else if (v.fuse) L.fn = opt ? c->tab->fused_lds_first[ws] : c->tab->fused_lds[ws];
     else L.fn = opt ? c->tab->stage_lds_opt[opt - 1][ws] : c->tab->stage_lds[ws];
   } else if (v.fuse) L.fn = c->tab->fused_direct[ws];
   else L.fn = c->tab->stage_direct[ws];
