@@ -202,9 +202,43 @@ def other_workload(name: str, steps: int, warmup: int, sizes=None, with_cpu: boo
                 "hbm_frac": v * bytes_per_cell_update(2, 4) / 1e9 / HBM_PEAK_GBS,
                 "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS["f32"],
                 "audit_drift": r["mass_energy_drift"]}
+    if name == "manifest":
+        return manifest_table(steps, warmup)
     if name == "convergence":
         return convergence_study(tuple(sizes) if sizes else (16, 32, 64, 128, 256, 512, 1024), with_cpu)
     raise SystemExit(f"unknown workload {name}")
+
+
+# The paper's hand-annotated individuals (table of codes annotated by hand):
+# whether the results of the interpolation (face states) and of the Riemann
+# solver (face fluxes) are stored and reused (Manifest) or recomputed where
+# used (Delayed).  Here the stored values live in LDS within a tile; all four
+# share one launch shape (32 x 16 cells, 256 threads, one launch per stage).
+MANIFEST_POINTS = (
+    ("Izanami (D,D)", dict(tile=(32, 16), lds=0, fuse=0, waves_per_eu=0, threads=256)),
+    ("Iwatsuchibiko (M,D)", dict(tile=(32, 16), lds=1, fuse=0, waves_per_eu=0, threads=256, manifest=1)),
+    ("Shinatsuhiko (D,M)", dict(tile=(32, 16), lds=1, fuse=0, waves_per_eu=0, threads=256, manifest=0)),
+    ("Hayaakitsuhime (M,M)", dict(tile=(32, 16), lds=1, fuse=0, waves_per_eu=0, threads=256, manifest=2)),
+)
+
+
+def manifest_table(steps: int, warmup: int):
+    """KH 2048^2 in FP32 and FP64 through the four Manifest/Delayed points."""
+    from paper_1204_4779_amd import inputs
+    pr = inputs.kelvin_helmholtz_2d(N, seed=1204)
+    rows = []
+    for name, var in MANIFEST_POINTS:
+        row = {"individual": name, "variant": var}
+        for dtype in ("f32", "f64"):
+            r = run_gpu(pr.U, dtype, var, steps, warmup)
+            v = N * N * r["steps"][0] / (r["event_ms"] / 1e3)
+            row[dtype] = {"value": v, "ms_per_step": r["event_ms"] / r["steps"][0],
+                          "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS[dtype]}
+            log(f"{name} {dtype}: {v / 1e9:.2f} G cell-updates/s")
+        rows.append(row)
+    best = max(rows, key=lambda r: r["f32"]["value"])
+    return {"workload": "manifest_points_kelvin_helmholtz_2d_2048x2048", "value": best["f32"]["value"],
+            "unit": "cell-updates/s", "dtype": "f32", "points": rows}
 
 
 def convergence_study(sizes=(16, 32, 64, 128, 256, 512, 1024), with_cpu: bool = True):
@@ -292,7 +326,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline FP32 only")
     ap.add_argument("--variant", type=str, default=None, help="JSON variant for the headline run")
     ap.add_argument("--workload", default="kh2048",
-                    choices=("kh2048", "sod1024", "box256", "box512", "batch512", "convergence"),
+                    choices=("kh2048", "sod1024", "box256", "box512", "batch512", "convergence", "manifest"),
                     help="kh2048 is the headline; the others print their own line")
     ap.add_argument("--sizes", type=int, nargs="*", default=None,
                     help="convergence workload: mesh sizes N (default 16 32 ... 1024)")

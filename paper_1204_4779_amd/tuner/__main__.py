@@ -4,6 +4,9 @@
         benchmark every statically valid variant on the GPU (resumes a partial DB)
     python -m paper_1204_4779_amd.tuner gain --db DB.jsonl [--seeds 15] [--frac 0.1]
         replay the database: MLP-guided vs random vs PAGSA search at the same budget
+    python -m paper_1204_4779_amd.tuner attribution --db DB.jsonl [--db MORE.jsonl]
+        component-wise artificial crossover between an initial individual and the
+        best one: what the launch configuration (C) and the storage choices (M) add
 """
 from __future__ import annotations
 
@@ -13,7 +16,7 @@ import sys
 
 import numpy as np
 
-from . import measure, search
+from . import analysis, measure, search
 from . import space as sp
 from .db import DB
 
@@ -25,8 +28,8 @@ def log(msg: str):
 def cmd_measure(a):
     wl = measure.WORKLOADS[a.workload]
     db = DB(a.db)
-    cands = search.candidates(wl.ndim, wl.esize)
-    log(f"{wl.name}: {len(sp.enumerate_space(wl.ndim))} raw variants, {len(cands)} statically valid, "
+    cands = search.candidates(wl.ndim, wl.esize, a.manifest)
+    log(f"{wl.name}: {len(sp.enumerate_space(wl.ndim, a.manifest))} raw variants, {len(cands)} statically valid, "
         f"{sum(1 for v in cands if sp.key(v) in db)} already in the database")
     bench = measure.Bench(wl, log=log)
     ev = search.LiveEvaluator(bench, db, wl.ndim, log=log)
@@ -84,17 +87,25 @@ def main(argv=None):
     m = sub.add_parser("measure")
     m.add_argument("--workload", default="box512", choices=sorted(measure.WORKLOADS))
     m.add_argument("--db", required=True)
+    m.add_argument("--manifest", action="store_true", help="include the LDS kernels' Manifest choices")
     g = sub.add_parser("gain")
     g.add_argument("--workload", default="box512", choices=sorted(measure.WORKLOADS))
     g.add_argument("--db", required=True)
     g.add_argument("--seeds", type=int, default=15)
     g.add_argument("--frac", type=float, default=0.1)
     g.add_argument("--out", default=None)
+    t = sub.add_parser("attribution")
+    t.add_argument("--workload", default="kh2048", choices=sorted(measure.WORKLOADS))
+    t.add_argument("--db", action="append", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "measure":
         cmd_measure(a)
-    else:
+    elif a.cmd == "gain":
         cmd_gain(a)
+    else:
+        wl = measure.WORKLOADS[a.workload]
+        dbs = [DB(p) for p in a.db]
+        log(json.dumps(analysis.attribution(dbs, wl.ndim, analysis.initial_individual(wl.ndim)), indent=1))
 
 
 if __name__ == "__main__":

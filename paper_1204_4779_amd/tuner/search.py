@@ -84,8 +84,8 @@ class LiveEvaluator:
                 "valid": r["valid"]}
 
 
-def candidates(ndim: int, esize: int) -> list:
-    return [v for v in sp.enumerate_space(ndim) if sp.statically_valid(v, ndim, esize)]
+def candidates(ndim: int, esize: int, manifest: bool = False) -> list:
+    return [v for v in sp.enumerate_space(ndim, manifest) if sp.statically_valid(v, ndim, esize)]
 
 
 def exhaustive(cands, evaluate) -> Trace:

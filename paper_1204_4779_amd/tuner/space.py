@@ -10,6 +10,13 @@ the hint (0 = compiler's choice, 3, 4, 5).  The paper's genome encodes Manifest 
 Delayed choices and launch configurations of generated code ("Tuning
 Targets"); here LDS staging and stage fusion are the storage-versus-recompute
 choices and tile and occupancy hint are the launch configuration.
+
+An optional axis adds the paper's own Manifest points to the LDS family
+("Annotating By Hand"): an LDS tile keeps face fluxes (manifest 0), face
+states with each cell solving both its faces (1), or both (2); keys of
+manifest 1 and 2 end in "_m1" / "_m2".  It is outside the genome: the
+search strategies run on the base space, the databases and the component
+attribution (`analysis.py`) see it.
 """
 from __future__ import annotations
 
@@ -47,7 +54,8 @@ def region(variant: dict, ndim: int, halo: int) -> int:
 
 
 def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
-    """Dynamic LDS of the LDS kernels: primitive region plus the largest face-flux block."""
+    """Dynamic LDS of the LDS kernels: primitive region plus the largest face-flux block,
+    plus lower and upper face values of the primitive region when face states are kept."""
     t = list(variant["tile"][:ndim])
     H = 4 if variant["fuse"] else 2
     vin = 1
@@ -62,7 +70,8 @@ def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
             f1 *= c1[b] + (1 if b == a else 0)
             f2 *= t[b] + (1 if b == a else 0)
         fmax = max(fmax, f1, f2)
-    return esize * (ndim + 2) * (vin + fmax)
+    kept = 2 * vin if variant.get("manifest", 0) else 0
+    return esize * (ndim + 2) * (vin + fmax + kept)
 
 
 def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
@@ -79,22 +88,26 @@ def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
     return max(c1, region(variant, ndim, 0)) <= KMAXR * threads_for(variant, ndim)
 
 
-def make_variant(tile, lds, fuse, waves, ndim) -> dict:
+def make_variant(tile, lds, fuse, waves, ndim, manifest: int = 0) -> dict:
     t = tuple(tile) + (1,) * (3 - len(tile))
     if lds == 2:
         t = (64,) + t[1:]
     v = {"tile": t, "lds": int(lds), "fuse": int(fuse), "waves_per_eu": int(waves)}
+    if manifest and lds == 1:
+        v["manifest"] = int(manifest)
     v["threads"] = threads_for(v, ndim)
     return v
 
 
-def enumerate_space(ndim: int) -> list:
+def enumerate_space(ndim: int, manifest: bool = False) -> list:
     out = []
     for tile in itertools.product(TILE_VALUES, repeat=ndim):
         for lds in (0, 1):
             for fuse in (0, 1):
                 for w in WAVE_VALUES:
                     out.append(make_variant(tile, lds, fuse, w, ndim))
+                    if manifest and lds == 1:
+                        out += [make_variant(tile, lds, fuse, w, ndim, m) for m in (1, 2)]
     if ndim == 2:
         for rows in TILE_VALUES:
             for fuse in (0, 1):
@@ -111,7 +124,9 @@ def enumerate_space(ndim: int) -> list:
 
 def key(variant: dict) -> str:
     t = variant["tile"]
-    return f"t{t[0]}x{t[1]}x{t[2]}_l{variant['lds']}_f{variant['fuse']}_w{variant['waves_per_eu']}"
+    k = f"t{t[0]}x{t[1]}x{t[2]}_l{variant['lds']}_f{variant['fuse']}_w{variant['waves_per_eu']}"
+    m = variant.get("manifest", 0)
+    return k + (f"_m{m}" if m else "")
 
 
 # ---- genome -------------------------------------------------------------------------------

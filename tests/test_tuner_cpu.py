@@ -184,3 +184,63 @@ def test_mlp_guided_ensemble_loop(monkeypatch):
     assert len(keys) == len(set(keys))                   # nothing benchmarked twice
     assert tr.spent - tr.evaluated[-1][2] < budget       # stops once the budget is spent
     assert tr.best_mu >= 0.9 * truth.best_mu             # the smooth synthetic optimum is found
+
+
+# ---- component attribution (artificial crossover) -----------------------------------
+
+def _product_db(ndim, c_of, m_of):
+    """A database whose score is a product of a launch-configuration factor and a
+    storage-choice factor: no synergy by construction."""
+    db = DB(None)
+    for v in search.candidates(ndim, 4, manifest=True):
+        mu = 1e9 * c_of(v) * m_of(v)
+        db.add({"key": sp.key(v), "variant": v, "valid": True, "mu": mu, "sigma": 0.0, "cost": 0.01})
+    return db
+
+
+def test_attribution_separates_independent_parts():
+    from paper_1204_4779_amd.tuner import analysis
+    c_of = lambda v: 1.0 + 0.01 * v["tile"][1] + 0.1 * (v["waves_per_eu"] == 3)
+    m_of = lambda v: {0: 1.0, 1: 2.0, 2: 4.0}[v["lds"]] * (1.5 if v["fuse"] else 1.0) * (0.5 if v.get("manifest") else 1.0)
+    db = _product_db(2, c_of, m_of)
+    init = analysis.initial_individual(2)
+    res = analysis.attribution([db], 2, init)
+    best = db.best()["variant"]
+    assert res["keys"]["best"] == sp.key(best)
+    # two parts: moving C into the initial individual is removing M from the best
+    assert res["keys"]["initial+C"] == res["keys"]["best-M"]
+    assert res["keys"]["initial+M"] == res["keys"]["best-C"]
+    assert res["add_M"] == pytest.approx(m_of(best) / m_of(init) - 1.0)
+    # multiplicative parts: the single-part log gains add up to the whole
+    assert res["log_additive_explained"] == pytest.approx(1.0)
+    assert res["speedup"] == pytest.approx(c_of(best) * m_of(best) / (c_of(init) * m_of(init)))
+
+
+def test_attribution_detects_synergy_and_missing_rows():
+    from paper_1204_4779_amd.tuner import analysis
+    # the launch configuration only matters once the storage choice is right
+    db = DB(None)
+    for v in search.candidates(2, 4):
+        mu = 1e9 * (3.0 * (1 + 0.02 * v["tile"][1]) if v["lds"] == 2 else 1.0)
+        db.add({"key": sp.key(v), "variant": v, "valid": True, "mu": mu, "sigma": 0.0, "cost": 0.01})
+    res = analysis.attribution([db], 2, analysis.initial_individual(2))
+    assert res["add_C"] == pytest.approx(0.0)
+    assert res["log_additive_explained"] < 1.0
+    # a crossover nobody measured is reported, not guessed
+    empty = DB(None)
+    for k in ("initial", "best"):
+        v = analysis.initial_individual(2) if k == "initial" else db.best()["variant"]
+        empty.add({"key": sp.key(v), "variant": v, "valid": True, "mu": 1e9 if k == "initial" else 2e9,
+                   "sigma": 0.0, "cost": 0.01})
+    res = analysis.attribution([empty], 2, analysis.initial_individual(2))
+    assert res["scores"]["initial+C"] is None and res["add_C"] is None
+    assert "log_additive_explained" not in res
+
+
+def test_manifest_axis_keys_and_lds_budget():
+    base = sp.make_variant((32, 16), 1, 0, 0, 2)
+    kept = sp.make_variant((32, 16), 1, 0, 0, 2, manifest=2)
+    assert sp.key(kept) == sp.key(base) + "_m2" and "manifest" not in base
+    assert sp.lds_bytes(kept, 2, 4) - sp.lds_bytes(base, 2, 4) == 4 * 4 * 2 * (36 * 20)
+    assert sp.make_variant((64, 16), 2, 1, 0, 2, manifest=1).get("manifest") is None
+    assert len(search.candidates(2, 4, manifest=True)) > len(search.candidates(2, 4))
