@@ -202,11 +202,93 @@ def other_workload(name: str, steps: int, warmup: int, sizes=None, with_cpu: boo
                 "hbm_frac": v * bytes_per_cell_update(2, 4) / 1e9 / HBM_PEAK_GBS,
                 "alu_frac": v * FLOPS_PER_CELL_UPDATE[2] / 1e12 / ALU_PEAK_TFLOPS["f32"],
                 "audit_drift": r["mass_energy_drift"]}
+    if name == "wave":
+        return wave_workload(with_cpu)
     if name == "manifest":
         return manifest_table(steps, warmup)
     if name == "convergence":
         return convergence_study(tuple(sizes) if sizes else (16, 32, 64, 128, 256, 512, 1024), with_cpu)
     raise SystemExit(f"unknown workload {name}")
+
+
+# Linear-wave kernel: flops per cell-update of the scheme and its energy term,
+# with the per-line constants folded (c^2 dt/dx^2, 1/(2dx), dx/2, c^2):
+# f update 2, g update 5, central difference 2, c^2 (df/dx)^2 2, mean of g
+# and its square 3, sum 1, times dx/2 1, accumulate 1.
+WAVE_FLOPS_PER_CELL_UPDATE = 17.0
+# LDS bytes per cell-update: f^{n+1} written once, both neighbours read.
+WAVE_LDS_BYTES_PER_CELL_UPDATE = 24.0
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12   # 128 B per clock per CU
+
+
+def wave_workload(with_cpu: bool = True, lines: int = 2048, n: int = 3072, steps: int = 2000):
+    """The linear-wave example: (1) the paper's experiment, one line per
+    n = 8 ... 3072 at c = 3.43, dt = dx / c, f = sin x, g = cos 3x, 10000
+    steps, energy fluctuation per n; (2) throughput: `lines` lines of n cells
+    (phases shifted per line) advanced `steps` steps in one launch."""
+    import numpy as np
+    import torch
+    from paper_1204_4779_amd import binding as pb
+    c = 3.43
+    fluct = {}
+    sizes = [8 << k for k in range(9)] + [3072]
+    fs, gs = [], []
+    for m in sizes:
+        x = np.arange(m) * (2 * math.pi / m)
+        fs.append(np.sin(x))
+        gs.append(np.cos(3 * x))
+    dxs = [2 * math.pi / m for m in sizes]
+    w = pb.WaveLines(fs, gs, c, dxs, [dx / c for dx in dxs], 10000)
+    w.advance(10000)
+    torch.cuda.synchronize()
+    for m, e in zip(sizes, w.energy):
+        e = e.cpu().numpy()
+        fluct[str(m)] = float((e.max() - e.min()) / e[0])
+    log(f"wave energy fluctuation over 10000 steps: {fluct}")
+    del w
+    # throughput
+    dx = 2 * math.pi / n
+    x = np.arange(n) * dx
+    fs = [np.sin(x + 0.001 * k) for k in range(lines)]
+    gs = [np.cos(3 * x + 0.002 * k) for k in range(lines)]
+    w = pb.WaveLines(fs, gs, c, dx, dx / c, steps)
+    w.prepare()
+    w.run(200)                        # warm-up, also the clock ramp
+    stream = torch.cuda.current_stream()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    w.run(steps)                      # one launch: `steps` steps of every line
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b)
+    cu = float(lines) * n * steps
+    v = cu / (ms / 1e3)
+    e = w.energy[0].cpu().numpy()
+    achieved = v * WAVE_FLOPS_PER_CELL_UPDATE / 1e12
+    out = {"workload": f"linear_wave_1d_{lines}x{n}_periodic_c3.43_fp64", "value": v, "unit": "cell-updates/s",
+           "dtype": "f64", "steps": steps, "ms": ms,
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": ALU_PEAK_TFLOPS["f64"],
+                        "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS["f64"], 4), "traffic": None,
+                        "kernel": "k_wave1d", "flops_per_cell_update": WAVE_FLOPS_PER_CELL_UPDATE},
+           "lds_roofline": {"achieved": round(v * WAVE_LDS_BYTES_PER_CELL_UPDATE / 1e12, 3), "peak": LDS_PEAK_TBS,
+                            "unit": "TB/s"},
+           "energy_fluctuation_line0": float((e.max() - e.min()) / e[0]),
+           "paper_experiment_energy_fluctuation": fluct}
+    if with_cpu:
+        import oracle.wave as ow
+        f0, g0 = ow.paper_initial(n)
+        t0 = time.perf_counter()
+        k = 0
+        f, g = f0, g0
+        while time.perf_counter() - t0 < 10.0:
+            f, g, _ = ow.step(f, g, c, dx, dx / c)
+            k += 1
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n * k / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one line of {n} cells, {k} FP64 steps (numpy), {el:.1f} s"}
+    return out
 
 
 # The paper's hand-annotated individuals (table of codes annotated by hand):
@@ -326,7 +408,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="headline FP32 only")
     ap.add_argument("--variant", type=str, default=None, help="JSON variant for the headline run")
     ap.add_argument("--workload", default="kh2048",
-                    choices=("kh2048", "sod1024", "box256", "box512", "batch512", "convergence", "manifest"),
+                    choices=("kh2048", "sod1024", "box256", "box512", "batch512", "convergence", "manifest",
+                             "wave"),
                     help="kh2048 is the headline; the others print their own line")
     ap.add_argument("--sizes", type=int, nargs="*", default=None,
                     help="convergence workload: mesh sizes N (default 16 32 ... 1024)")

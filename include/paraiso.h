@@ -278,6 +278,64 @@ int32_t paraiso_current(const paraiso_ctx* ctx, int32_t* idx);
  */
 int32_t paraiso_totals(paraiso_ctx* ctx, double* out);
 
+/*
+ * The linear-wave example (section "An Example of Orthotope Machine
+ * Data-Flow Graph"): f_t = g, g_t = c^2 f_xx on a periodic line of n cells,
+ * advanced by the paper's two-level scheme
+ *   f^{k+1}[i] = f^k[i] + dt g^k[i],
+ *   g^{k+1}[i] = g^k[i] + (c^2 dt / dx^2)(f^{k+1}[i+1] + f^{k+1}[i-1] - 2 f^{k+1}[i]),
+ * and, after every step, the discrete energy in the form of the paper's
+ * source listing
+ *   E^{k+1} = sum_i (c^2 ((f^{k+1}[i+1] - f^{k+1}[i-1]) / (2 dx))^2
+ *                    + ((g^k[i] + g^{k+1}[i]) / 2)^2) dx / 2,
+ * which at dt = dx / c is an exact invariant of the scheme (the paper finds
+ * it constant to about 1e-13 in FP64).  FP64 throughout.
+ *
+ * One line: n cells, 3 <= n <= PARAISO_WAVE_MAX_CELLS; c >= 0 and dt >= 0
+ * finite, dx > 0 finite; f and g device arrays of n doubles, read at the
+ * start and overwritten with the final state; energy a device array of
+ * `steps` doubles (E after each step) or NULL.  Arrays 8-byte aligned,
+ * owned by the caller, not overlapping.
+ */
+#define PARAISO_WAVE_MAX_CELLS 4096
+typedef struct paraiso_wave {
+  int64_t n;
+  double c;
+  double dx;
+  double dt;
+  double* f;
+  double* g;
+  double* energy;
+} paraiso_wave;
+
+/* Bytes of device workspace paraiso_wave_advance needs for `count` lines
+ * (the device copy of the line table).  Errors: INVALID_ARG. */
+int32_t paraiso_wave_workspace_bytes(int32_t count, size_t* bytes);
+
+/*
+ * Validate `count` lines and copy their table into `workspace`, a device
+ * buffer of at least paraiso_wave_workspace_bytes(count) bytes, 256-byte
+ * aligned (synchronous on `hip_stream`).
+ * Errors: INVALID_ARG (null pointers, count < 1, a line out of range: the
+ * message names it), WORKSPACE, HIP.
+ */
+int32_t paraiso_wave_prepare(const paraiso_wave* lines, int32_t count, void* workspace, size_t workspace_bytes,
+                             void* hip_stream);
+
+/*
+ * Advance the `count` lines prepared in `workspace` by `steps` steps each,
+ * one workgroup per line, enqueued on `hip_stream` (asynchronous).  Each
+ * line's energy array receives E after each of these steps (from index 0).
+ * The energy sums are taken in a fixed order: results are bitwise
+ * reproducible.  Errors: INVALID_ARG (null workspace, count < 1, steps < 0,
+ * misaligned workspace), HIP.
+ */
+int32_t paraiso_wave_run(const void* workspace, int32_t count, int64_t steps, void* hip_stream);
+
+/* paraiso_wave_prepare, then paraiso_wave_run. */
+int32_t paraiso_wave_advance(const paraiso_wave* lines, int32_t count, int64_t steps, void* workspace,
+                             size_t workspace_bytes, void* hip_stream);
+
 /* Release the context (never the caller's buffers).  NULL is a no-op. */
 int32_t paraiso_destroy(paraiso_ctx* ctx);
 

@@ -35,7 +35,8 @@ EXPORTS = ("paraiso_workspace_bytes", "paraiso_init", "paraiso_set_variant", "pa
            "paraiso_default_variant", "paraiso_cfl_dt", "paraiso_step", "paraiso_advance",
            "paraiso_current", "paraiso_totals", "paraiso_destroy", "paraiso_last_error",
            "paraiso_version", "paraiso_set_analytic", "paraiso_exact_state", "paraiso_set_time", "paraiso_get_time",
-           "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
+           "paraiso_wave_workspace_bytes", "paraiso_wave_prepare", "paraiso_wave_run",
+           "paraiso_wave_advance", "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
            "paraiso_mlp_adam")
 
 
@@ -64,6 +65,14 @@ class paraiso_analytic(ctypes.Structure):
         a = cls()
         a.kind, a.reserved, a.angle, a.amplitude = int(kind), 0, float(angle), float(amplitude)
         return a
+
+
+WAVE_MAX_CELLS = 4096
+
+
+class paraiso_wave(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("c", ctypes.c_double), ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("f", ctypes.c_void_p), ("g", ctypes.c_void_p), ("energy", ctypes.c_void_p)]
 
 
 class paraiso_variant(ctypes.Structure):
@@ -117,6 +126,10 @@ def load(path: str | None = None):
         "paraiso_set_analytic": ([vp, i32, ctypes.POINTER(paraiso_analytic)], i32),
         "paraiso_exact_state": ([vp, i32, dbl, i32], i32),
         "paraiso_set_time": ([vp, dp], i32),
+        "paraiso_wave_workspace_bytes": ([i32, ctypes.POINTER(szt)], i32),
+        "paraiso_wave_prepare": ([ctypes.POINTER(paraiso_wave), i32, vp, szt, vp], i32),
+        "paraiso_wave_run": ([vp, i32, i64, vp], i32),
+        "paraiso_wave_advance": ([ctypes.POINTER(paraiso_wave), i32, i64, vp, szt, vp], i32),
         "paraiso_get_time": ([vp, dp], i32),
         "paraiso_destroy": ([vp], i32),
         "paraiso_last_error": ([], ctypes.c_char_p),
@@ -227,6 +240,29 @@ def paraiso_get_time(ctx: int, count: int = 1) -> list:
     out = (ctypes.c_double * count)()
     _check(load().paraiso_get_time(ctypes.c_void_p(ctx), out))
     return list(out)
+
+
+def paraiso_wave_workspace_bytes(count: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load().paraiso_wave_workspace_bytes(int(count), ctypes.byref(out)))
+    return out.value
+
+
+def paraiso_wave_prepare(lines, workspace_ptr: int, workspace_bytes: int, stream_ptr: int) -> None:
+    arr = (paraiso_wave * len(lines))(*lines)
+    _check(load().paraiso_wave_prepare(arr, len(lines), ctypes.c_void_p(workspace_ptr), int(workspace_bytes),
+                                       ctypes.c_void_p(stream_ptr)))
+
+
+def paraiso_wave_run(workspace_ptr: int, count: int, steps: int, stream_ptr: int) -> None:
+    _check(load().paraiso_wave_run(ctypes.c_void_p(workspace_ptr), int(count), int(steps),
+                                   ctypes.c_void_p(stream_ptr)))
+
+
+def paraiso_wave_advance(lines, steps: int, workspace_ptr: int, workspace_bytes: int, stream_ptr: int) -> None:
+    arr = (paraiso_wave * len(lines))(*lines)
+    _check(load().paraiso_wave_advance(arr, len(lines), int(steps), ctypes.c_void_p(workspace_ptr),
+                                       int(workspace_bytes), ctypes.c_void_p(stream_ptr)))
 
 
 def paraiso_destroy(ctx: int) -> None:
@@ -404,3 +440,52 @@ class Solver:
 
     def time(self) -> list:
         return paraiso_get_time(self.ctx, self.count)
+
+
+class WaveLines:
+    """A batch of periodic lines for paraiso_wave_advance: f, g and the energy
+    history as FP64 torch tensors on the current device, torch's current stream."""
+
+    def __init__(self, fs, gs, c, dx, dt, steps_capacity: int, device=None):
+        import torch
+        self.torch = torch
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        count = len(fs)
+        per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * count
+        self.c, self.dx, self.dt = per(c), per(dx), per(dt)
+        self.f = [torch.as_tensor(v, dtype=torch.float64).to(dev).contiguous() for v in fs]
+        self.g = [torch.as_tensor(v, dtype=torch.float64).to(dev).contiguous() for v in gs]
+        self.energy = [torch.zeros(max(int(steps_capacity), 1), dtype=torch.float64, device=dev)
+                       for _ in range(count)]
+        self.capacity = int(steps_capacity)
+        self.ws_bytes = paraiso_wave_workspace_bytes(count)
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+
+    def prepare(self, record_energy: bool = True):
+        """Upload the line table; run() then enqueues steps without host work."""
+        paraiso_wave_prepare(self._lines(record_energy), self.ws_ptr, self.ws_bytes,
+                             self.torch.cuda.current_stream(self.device).cuda_stream)
+        self.recording = record_energy
+
+    def run(self, steps: int):
+        if self.recording and steps > self.capacity:
+            raise ValueError("more steps than the energy buffers hold")
+        paraiso_wave_run(self.ws_ptr, len(self.f), steps, self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _lines(self, record_energy: bool):
+        lines = []
+        for k in range(len(self.f)):
+            w = paraiso_wave()
+            w.n, w.c, w.dx, w.dt = self.f[k].numel(), self.c[k], self.dx[k], self.dt[k]
+            w.f, w.g = self.f[k].data_ptr(), self.g[k].data_ptr()
+            w.energy = self.energy[k].data_ptr() if record_energy else None
+            lines.append(w)
+        return lines
+
+    def advance(self, steps: int, record_energy: bool = True):
+        if record_energy and steps > self.capacity:
+            raise ValueError("more steps than the energy buffers hold")
+        stream = self.torch.cuda.current_stream(self.device)
+        paraiso_wave_advance(self._lines(record_energy), steps, self.ws_ptr, self.ws_bytes, stream.cuda_stream)

@@ -169,3 +169,35 @@ def test_header_compiles_as_c_and_cpp(tmp_path):
         r = subprocess.run([cc, std, "-Wall", "-Werror", "-fsyntax-only", "-I", inc] + lang + [str(src)],
                            capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_wave_entry_points_validate_before_any_device_work(lib):
+    import ctypes
+    assert pb.paraiso_wave_workspace_bytes(1) == 256
+    assert pb.paraiso_wave_workspace_bytes(10) >= 10 * 64
+    with pytest.raises(pb.ParaisoError):
+        pb.paraiso_wave_workspace_bytes(0)
+    ws = 0x100000          # never touched: every case below fails validation first
+
+    def line(**kw):
+        w = pb.paraiso_wave()
+        w.n, w.c, w.dx, w.dt, w.f, w.g, w.energy = 64, 1.0, 0.1, 0.05, 0x2000, 0x4000, None
+        for k, v in kw.items():
+            setattr(w, k, v)
+        return w
+    bad = [dict(n=2), dict(n=4097), dict(c=-1.0), dict(c=float("nan")), dict(dx=0.0), dict(dt=float("inf")),
+           dict(f=None), dict(g=0x4004), dict(energy=0x6001)]
+    for kw in bad:
+        with pytest.raises(pb.ParaisoError) as ei:
+            pb.paraiso_wave_advance([line(**kw)], 10, ws, 256, 0)
+        assert ei.value.code == pb.ERR_INVALID_ARG, kw
+        assert "line 0" in str(ei.value), kw
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_wave_advance([line()], -1, ws, 256, 0)
+    assert ei.value.code == pb.ERR_INVALID_ARG
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_wave_advance([line()], 1, ws + 8, 256, 0)
+    assert ei.value.code == pb.ERR_INVALID_ARG
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_wave_advance([line()] * 8, 1, ws, 256, 0)
+    assert ei.value.code == pb.ERR_WORKSPACE
