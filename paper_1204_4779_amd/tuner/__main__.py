@@ -7,16 +7,22 @@
     python -m paper_1204_4779_amd.tuner attribution --db DB.jsonl [--db MORE.jsonl]
         component-wise artificial crossover between an initial individual and the
         best one: what the launch configuration (C) and the storage choices (M) add
+    python -m paper_1204_4779_amd.tuner service --workload kh2048 --db OUT.jsonl --workers 3 --budget 20
+        asynchronous PAGSA: worker processes over one shared database (live on the
+        GPU, benchmarks serialised by a device lock; or --replay DB.jsonl)
+    python -m paper_1204_4779_amd.tuner lineage --db OUT.jsonl
+        family-tree analyses: contribution distance, ranks, chi-squared and Markov tests
 """
 from __future__ import annotations
 
 import argparse
 import json
 import sys
+import time
 
 import numpy as np
 
-from . import analysis, measure, search
+from . import analysis, lineage, measure, search, service
 from . import space as sp
 from .db import DB
 
@@ -94,6 +100,16 @@ def main(argv=None):
     g.add_argument("--seeds", type=int, default=15)
     g.add_argument("--frac", type=float, default=0.1)
     g.add_argument("--out", default=None)
+    sv = sub.add_parser("service")
+    sv.add_argument("--workload", default="kh2048", choices=sorted(measure.WORKLOADS))
+    sv.add_argument("--db", required=True)
+    sv.add_argument("--workers", type=int, default=3)
+    sv.add_argument("--budget", type=float, default=20.0, help="benchmark seconds per worker")
+    sv.add_argument("--seed", type=int, default=0)
+    sv.add_argument("--replay", default=None, help="measured database to answer from instead of the GPU")
+    sv.add_argument("--time-scale", type=float, default=0.0)
+    ln = sub.add_parser("lineage")
+    ln.add_argument("--db", action="append", required=True)
     t = sub.add_parser("attribution")
     t.add_argument("--workload", default="kh2048", choices=sorted(measure.WORKLOADS))
     t.add_argument("--db", action="append", required=True)
@@ -102,6 +118,14 @@ def main(argv=None):
         cmd_measure(a)
     elif a.cmd == "gain":
         cmd_gain(a)
+    elif a.cmd == "service":
+        wl = measure.WORKLOADS[a.workload]
+        spec = ("replay", a.replay, a.time_scale) if a.replay else ("live", a.workload)
+        t0 = time.time()
+        res = service.run_service(a.db, a.workers, wl.ndim, wl.esize, spec, a.budget, a.seed)
+        log(json.dumps({"workers": res, "wall_s": time.time() - t0}))
+    elif a.cmd == "lineage":
+        log(json.dumps(lineage.report([DB(p) for p in a.db]), indent=1))
     else:
         wl = measure.WORKLOADS[a.workload]
         dbs = [DB(p) for p in a.db]

@@ -157,6 +157,45 @@ def crossover(a: str, b: str, rng) -> str:
     return a[:i] + b[i:j] + a[j:]
 
 
+BIRTHS = ("mutation", "crossover", "triangulation")
+
+
+def pagsa_birth(known: dict, rng, taken=()):
+    """One birth of the paper's genetic simulated annealing.  `known` maps the
+    genomes in the database to (mu, sigma) (mu = 0 for invalid ones); at a
+    random temperature, one to three distinct parents are drawn by the draw
+    weights and combined by mutation, crossover or triangulation (probability
+    1/3 each; triangulation orders its parents Base < Secondary < Primary by
+    score).  A child already known, or in `taken` (being benchmarked
+    elsewhere), is redrawn at a 1.2 times higher temperature.  Returns
+    (child genome, parent genomes, method) or None after 200 draws.  The
+    caller makes sure some mu is positive."""
+    genomes = list(known)
+    mus = np.array([known[g][0] for g in genomes])
+    sig = np.array([known[g][1] for g in genomes])
+    T = draw_temperature(mus, sig, rng)
+    method = int(rng.integers(0, 3))
+    need = (1, 2, 3)[method]
+    for _ in range(200):
+        w = draw_weights(mus, sig, T)
+        idx = rng.choice(len(genomes), size=need, replace=True, p=w)
+        if len(set(idx.tolist())) < need:
+            continue  # two parents coincide: draw again
+        par = [genomes[i] for i in idx]
+        if method == 0:
+            c = mutate(par[0], rng)
+        elif method == 1:
+            c = crossover(par[0], par[1], rng)
+        else:
+            base, sec, prim = sorted(par, key=lambda g: known[g][0])
+            c = triangulate(base, sec, prim)
+        if c in known or c in taken:
+            T *= 1.2  # duplicate genome: retry at a higher temperature
+            continue
+        return c, par, BIRTHS[method]
+    return None
+
+
 def pagsa(cands, evaluate, budget: float, rng, ndim: int, seed_variants) -> Trace:
     tr = Trace("pagsa")
     valid_keys = {sp.key(v) for v in cands}
@@ -176,33 +215,9 @@ def pagsa(cands, evaluate, budget: float, rng, ndim: int, seed_variants) -> Trac
             break
         run(v, birth="seed")
     while tr.spent < budget:
-        genomes = list(known)
-        mus = np.array([known[g][0] for g in genomes])
-        sig = np.array([known[g][1] for g in genomes])
-        if mus.max() <= 0:
+        if max(m for m, _ in known.values()) <= 0:
             break
-        T = draw_temperature(mus, sig, rng)
-        method = int(rng.integers(0, 3))
-        need = (1, 2, 3)[method]
-        child = None
-        for _ in range(200):
-            w = draw_weights(mus, sig, T)
-            idx = rng.choice(len(genomes), size=need, replace=True, p=w)
-            if len(set(idx.tolist())) < need:
-                continue  # two parents coincide: draw again
-            par = [genomes[i] for i in idx]
-            if method == 0:
-                c = mutate(par[0], rng)
-            elif method == 1:
-                c = crossover(par[0], par[1], rng)
-            else:
-                base, sec, prim = sorted(par, key=lambda g: known[g][0])
-                c = triangulate(base, sec, prim)
-            if c in known:
-                T *= 1.2  # duplicate genome: retry at a higher temperature
-                continue
-            child = (c, par, ("mutation", "crossover", "triangulation")[method])
-            break
+        child = pagsa_birth(known, rng)
         if child is None:
             # every draw produced a known genome; fall back to an unseen random one
             unseen = [v for v in cands if sp.encode(v, ndim) not in known]
