@@ -176,7 +176,8 @@ int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
  * paraiso_init): 1D the resident kernel when every mesh fits one
  * workgroup, else LDS tiles; 2D the fused register march when every mesh is
  * periodic on both axes, else LDS tiles; 3D the register march.  Any mesh
- * with an analytic axis: unfused LDS tiles; first order: LDS tiles. */
+ * with an analytic axis: in 2D the one-stage register march, else unfused
+ * LDS tiles; first order: LDS tiles. */
 int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
 
 /*
@@ -229,8 +230,10 @@ int32_t paraiso_advance(paraiso_ctx* ctx, double t_end, double cfl, int64_t max_
  *                         s = 1/2, the exact Riemann solution at (s - 1/2)/t
  *                         (the star state solved on the host in FP64).
  * angle must be 0 in 1D ("coaxial"; the "oblique" tests use pi/3).
- * Meshes with an analytic axis run on the unfused LDS-tile kernel
- * (variant lds = 1, fuse = 0; the default picks it).
+ * Meshes with an analytic axis run on the unfused LDS-tile kernel (variant
+ * lds = 1, fuse = 0) or, in 2D, the one-stage register march (lds = 2,
+ * fuse = 0, the default), which reads its ghost cells from arrays in the
+ * workspace that a small kernel fills before every step.
  */
 typedef struct paraiso_analytic {
   int32_t kind;      /* PARAISO_ENTROPY_WAVE, PARAISO_SOUND_WAVE or PARAISO_SHOCK_TUBE */

@@ -97,4 +97,44 @@ __global__ void __launch_bounds__(256) k_exact_state(Args a, int m, double t, in
   U.f[D + 1][c] = (T)(v[D + 1] * M.inv_gm1 + 0.5 * v[0] * ke);
 }
 
+// Exact ghost cells of the 2D analytic meshes for one step: stage 1 at the
+// step's time t, stage 2 at t + dt/2 (the times the stages' inputs stand
+// for), as conserved values rounded once to T.  Grid: meshes along x, the
+// ghost cells of a mesh spread over the blocks along y.
+template <typename T>
+__global__ void __launch_bounds__(256) k_analytic_ghosts(Args a) {
+  const int m = blockIdx.x;
+  const MeshDev& M = a.meshes[m];
+  if (!M.ghost || M.an.kind == 0) return;
+  bool active;
+  const double dt = step_dt(a, m, active);
+  if (!active) return;
+  const double t0 = a.ctl[m].t[a.ring];
+  const int nx = M.n[0], ny = M.n[1];
+  const int S = ghost_stride(nx, ny);
+  T* gh = reinterpret_cast<T*>(M.ghost);
+  for (int l = blockIdx.y * blockDim.x + threadIdx.x; l < 2 * S; l += gridDim.y * blockDim.x) {
+    const int st = l / S, idx = l - st * S;
+    int c, r;
+    if (idx < 4 * (ny + 4)) {
+      const int j = idx / (ny + 4);
+      r = idx - j * (ny + 4) - 2;
+      c = j < 2 ? j - 2 : nx + j - 2;
+    } else {
+      const int i2 = idx - 4 * (ny + 4);
+      const int j = i2 / (nx + 4);
+      c = i2 - j * (nx + 4) - 2;
+      r = j < 2 ? j - 2 : ny + j - 2;
+    }
+    double v[4];
+    exact_prims<double, 2>(M, (c + 0.5) * M.dx[0], (r + 0.5) * M.dx[1], st == 0 ? t0 : t0 + 0.5 * dt, v);
+    const double ke = v[1] * v[1] + v[2] * v[2];
+    T* out = gh + (size_t)st * 4 * S + idx;
+    out[0] = (T)v[0];
+    out[S] = (T)(v[0] * v[1]);
+    out[2 * S] = (T)(v[0] * v[2]);
+    out[3 * S] = (T)(v[3] * M.inv_gm1 + 0.5 * v[0] * ke);
+  }
+}
+
 }  // namespace paraiso

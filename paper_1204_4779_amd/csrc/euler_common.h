@@ -50,7 +50,14 @@ struct MeshDev {
   double inv_gm1;          // 1 / (gamma - 1)
   double vol;              // cell volume
   Analytic an;             // for meshes with an analytic boundary
+  void* ghost;             // 2D analytic meshes: the exact solution on the ghost cells of both
+                           // stages, [stage][field][ghost cell] (see ghost_stride), in the workspace
 };
+
+// Ghost cells of a 2D mesh kept for the register march: the 2 columns on
+// each side for every row from -2 to ny+1 (4 (ny+4) cells), then the 2 rows
+// on each side for every column from -2 to nx+1 (4 (nx+4) cells).
+__host__ __device__ constexpr int ghost_stride(int nx, int ny) { return 4 * (ny + 4) + 4 * (nx + 4); }
 
 struct Ctl {
   double t[3];

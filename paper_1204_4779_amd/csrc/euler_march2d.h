@@ -126,7 +126,7 @@ __device__ __forceinline__ void pipe_push(RowPipe<T>& P, const T* c, const Gas<T
 // shifted by plain assignments every push; the caller unrolls the steady
 // state six-fold, so that after inlining the shifts are register renames
 // and the loop carries no copies (every ring period divides six).
-template <typename T, bool FUSED>
+template <typename T, bool FUSED, bool AN = false>
 struct StripMarch {
   Fields<T, 2> U0, Uin, Uout;
   Gas<T> g;
@@ -148,6 +148,13 @@ struct StripMarch {
   T* share_out;
   const T* share_in;
   int lane;
+  // analytic boundaries (AN, one stage): the stage's input ghost cells come
+  // from the ghost arrays (exact solution at the time of the stage's input)
+  const T* gsrc;  // this stage's set, field 0
+  int gS;         // field stride of the ghost arrays
+  int gx;         // lane's column + 2, clamped to [0, nx + 3]: its place in a ghost row
+  int gxj;        // lane's ghost column 0..3 on an analytic x axis, else -1
+  bool grows;     // y is analytic
 
   // Row offsets are wave-uniform (scalar registers) and the column a 32-bit
   // unsigned byte offset per lane, so each access is one global load or
@@ -165,10 +172,30 @@ struct StripMarch {
   }
 
   __device__ __forceinline__ void load_row(int k, T* u) const {
+    if constexpr (AN) {
+      const int r = first + k;
+      if (grows && (r < 0 || r >= ny)) {
+        int j = r < 0 ? r + 2 : r - ny + 2;  // ghost row 0..3 (clamped: the prefetch may run past)
+        j = j < 0 ? 0 : (j > 3 ? 3 : j);
+        const T* src = gsrc + 4 * (ny + 4) + j * (nx + 4) + gx;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = src[q * gS];
+        return;
+      }
+    }
     const int ro = map_index(first + k, ny, bcy) * nx;
     const unsigned c = lane_bytes();
 #pragma unroll
     for (int q = 0; q < 4; ++q) u[q] = *at(Uin.f[q] + ro, c);
+    if constexpr (AN) {
+      if (gxj >= 0) {
+        int rr = first + k + 2;
+        rr = rr < 0 ? 0 : (rr > ny + 3 ? ny + 3 : rr);
+        const T* src = gsrc + gxj * (ny + 4) + rr;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = src[q * gS];
+      }
+    }
   }
 
   __device__ __forceinline__ void emit(int y, const T* u) {
@@ -288,12 +315,14 @@ struct StripMarch {
 };
 
 // Fused step (FUSED, periodic meshes) or one stage (!FUSED, periodic or
-// outflow: the stage's ghost cells are clamped loads of its input).
+// outflow: the stage's ghost cells are clamped loads of its input; with AN
+// also analytic, ghost cells from the ghost arrays k_analytic_ghosts fills).
 // Block = threads/64 waves stacked along y, `rows` rows each: the block
 // tile is (64 - 2H) columns by march2d_item_rows(waves, rows) rows (the
 // last wave of a sharing block takes rows - 2).
-template <typename T, int W, bool FUSED>
+template <typename T, int W, bool FUSED, bool AN = false>
 __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, LdsGeom G) {
+  static_assert(!(AN && FUSED), "analytic boundaries: one stage per launch");
   constexpr int H = FUSED ? 4 : 2;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_red[16];
@@ -338,7 +367,7 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
         }
       }
     } else if (y0 < y1) {
-      StripMarch<T, FUSED> S;
+      StripMarch<T, FUSED, AN> S;
       S.U0 = uniform(U0);
       S.Uin = uniform((FUSED || a.stage == 1) ? U0 : fields<T, 2>(M.w));
       S.Uout = uniform(Uout);
@@ -362,6 +391,16 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
       S.qmax = 0.0;
       S.bad = false;
       S.lane = lane;
+      if constexpr (AN) {
+        S.gS = ghost_stride(nx, ny);
+        S.gsrc = reinterpret_cast<const T*>(M.ghost) + (a.stage == 2 ? 4 * S.gS : 0);
+        const int xc = x0 - H + lane;
+        int gj = xc < 0 ? xc + 2 : xc - nx + 2;
+        gj = gj < 0 ? 0 : (gj > 3 ? 3 : gj);
+        S.gxj = (M.bc[0] == kAnalytic && (xc < 0 || xc >= nx)) ? gj : -1;
+        S.gx = xc + 2 < 0 ? 0 : (xc + 2 > nx + 3 ? nx + 3 : xc + 2);
+        S.grows = M.bc[1] == kAnalytic;
+      }
       // fused: a wave that is not the block's last reads the next wave's
       // first four stage-1 rows; every wave but the first leaves its own
       S.share_out = (share && wave > 0) ? lds_rows + wave * 1024 : nullptr;

@@ -26,12 +26,15 @@ const KernelTable* table_f32_2() {
        (const void*)k_march2d<float, 4, true>, (const void*)k_march2d<float, 5, true>},
       {(const void*)k_march2d<float, 0, false>, (const void*)k_march2d<float, 3, false>,
        (const void*)k_march2d<float, 4, false>, (const void*)k_march2d<float, 5, false>},
+      {(const void*)k_march2d<float, 0, false, true>, (const void*)k_march2d<float, 3, false, true>,
+       (const void*)k_march2d<float, 4, false, true>, (const void*)k_march2d<float, 5, false, true>},
       {nullptr, nullptr, nullptr, nullptr},
       nullptr,
       (const void*)k_cfl<float, 2>,
       (const void*)k_totals_partial<float, 2>,
       (const void*)k_totals_final<2>,
       (const void*)k_exact_state<float, 2>,
+      (const void*)k_analytic_ghosts<float>,
       (int)sizeof(float),
   };
   return &t;

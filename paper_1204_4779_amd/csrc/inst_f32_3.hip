@@ -24,6 +24,7 @@ const KernelTable* table_f32_3() {
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      {nullptr, nullptr, nullptr, nullptr},
       {(const void*)k_march3d<float, 0>, (const void*)k_march3d<float, 3>, (const void*)k_march3d<float, 4>,
        (const void*)k_march3d<float, 5>},
       nullptr,
@@ -31,6 +32,7 @@ const KernelTable* table_f32_3() {
       (const void*)k_totals_partial<float, 3>,
       (const void*)k_totals_final<3>,
       (const void*)k_exact_state<float, 3>,
+      nullptr,
       (int)sizeof(float),
   };
   return &t;

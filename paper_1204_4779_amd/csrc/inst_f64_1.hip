@@ -25,11 +25,13 @@ const KernelTable* table_f64_1() {
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      {nullptr, nullptr, nullptr, nullptr},
       (const void*)k_resident1d<double>,
       (const void*)k_cfl<double, 1>,
       (const void*)k_totals_partial<double, 1>,
       (const void*)k_totals_final<1>,
       (const void*)k_exact_state<double, 1>,
+      nullptr,
       (int)sizeof(double),
   };
   return &t;

@@ -26,12 +26,15 @@ const KernelTable* table_f64_2() {
        (const void*)k_march2d<double, 4, true>, (const void*)k_march2d<double, 5, true>},
       {(const void*)k_march2d<double, 0, false>, (const void*)k_march2d<double, 3, false>,
        (const void*)k_march2d<double, 4, false>, (const void*)k_march2d<double, 5, false>},
+      {(const void*)k_march2d<double, 0, false, true>, (const void*)k_march2d<double, 3, false, true>,
+       (const void*)k_march2d<double, 4, false, true>, (const void*)k_march2d<double, 5, false, true>},
       {nullptr, nullptr, nullptr, nullptr},
       nullptr,
       (const void*)k_cfl<double, 2>,
       (const void*)k_totals_partial<double, 2>,
       (const void*)k_totals_final<2>,
       (const void*)k_exact_state<double, 2>,
+      (const void*)k_analytic_ghosts<double>,
       (int)sizeof(double),
   };
   return &t;

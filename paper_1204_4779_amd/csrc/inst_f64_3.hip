@@ -24,6 +24,7 @@ const KernelTable* table_f64_3() {
       PARAISO_SET(k_fused_direct),
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
+      {nullptr, nullptr, nullptr, nullptr},
       {(const void*)k_march3d<double, 0>, (const void*)k_march3d<double, 3>, (const void*)k_march3d<double, 4>,
        (const void*)k_march3d<double, 5>},
       nullptr,
@@ -31,6 +32,7 @@ const KernelTable* table_f64_3() {
       (const void*)k_totals_partial<double, 3>,
       (const void*)k_totals_final<3>,
       (const void*)k_exact_state<double, 3>,
+      nullptr,
       (int)sizeof(double),
   };
   return &t;

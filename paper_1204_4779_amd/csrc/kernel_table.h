@@ -17,12 +17,14 @@ struct KernelTable {
   const void* fused_direct[4];
   const void* march_fused[4];  // 2D register march (null for other dimensions)
   const void* march_stage[4];
+  const void* march_stage_an[4];  // one stage with analytic ghost cells from the ghost arrays (2D)
   const void* march3d_stage[4];  // 3D register march, one stage (null for other dimensions)
   const void* resident1d;        // whole-advance kernel of small 1D meshes (null otherwise)
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;
   const void* exact_state;       // exact solution of an analytic problem into a state buffer
+  const void* analytic_ghosts;   // the ghost arrays of 2D analytic meshes for one step (2D)
   int elem_bytes;
 };
 

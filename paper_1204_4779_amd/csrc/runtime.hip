@@ -165,8 +165,15 @@ int validate_meshes(const paraiso_mesh* ms, int count) {
   return PARAISO_OK;
 }
 
+// Ghost arrays of a 2D mesh with an analytic axis (both stages, d+2 fields).
+size_t ghost_bytes(const paraiso_mesh& m) {
+  if (m.ndim != 2 || !has_analytic(m)) return 0;
+  const size_t esize = m.dtype == PARAISO_F32 ? 4 : 8;
+  return align256(2 * 4 * (size_t)ghost_stride((int)m.n[0], (int)m.n[1]) * esize);
+}
+
 struct Layout {
-  size_t meshes = 0, ctl = 0, params = 0, dt = 0, queue = 0, out = 0, partials = 0, u1 = 0, total = 0;
+  size_t meshes = 0, ctl = 0, params = 0, dt = 0, queue = 0, out = 0, partials = 0, u1 = 0, ghost = 0, total = 0;
   int total_chunks = 0;
 };
 
@@ -193,6 +200,8 @@ Layout layout_of(const paraiso_mesh* ms, int count) {
   L.u1 = off;
   const size_t esz = ms[0].dtype == PARAISO_F32 ? 4 : 8;
   for (int m = 0; m < count; ++m) off += (size_t)(ms[m].ndim + 2) * align256((size_t)cells_of(ms[m]) * esz);
+  L.ghost = off;
+  for (int m = 0; m < count; ++m) off += ghost_bytes(ms[m]);
   L.total = off;
   return L;
 }
@@ -225,6 +234,8 @@ struct paraiso_ctx {
   const KernelTable* tab = nullptr;
   paraiso_variant var{};
   bool fused = false, lds = false, persistent = false, resident = false;
+  bool ghosts = false;  // the variant reads the ghost arrays: fill them before every step
+  int ghost_blocks = 1;  // blocks per mesh of the ghost fill (one ghost cell per thread)
   int nitems = 0;
   int xcd_begin[9] = {};
   LdsGeom geom{};
@@ -289,6 +300,11 @@ int enqueue_step(const paraiso_ctx* c, int cur, int ring, bool explicit_dt, hipS
     a.stage = 0;
     a.cfl = explicit_dt ? 0 : 1;
     return launch(c->step, a, c->geom, s);
+  }
+  if (c->ghosts) {
+    // exact ghost cells of both stages of this step, from the device-held t and dt
+    void* args[] = {(void*)&a};
+    HIP_TRY(hipLaunchKernel(c->tab->analytic_ghosts, dim3(c->count, c->ghost_blocks), dim3(256), args, 0, s));
   }
   a.stage = 1;
   a.cfl = 0;
@@ -414,8 +430,9 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
         return why = "3D register march: threads must be 64 * tile[1]", PARAISO_ERR_UNSUPPORTED;
     }
   }
-  if (any_analytic(c->meshes.data(), c->count) && (v.lds != 1 || v.fuse != 0))
-    return why = "analytic boundaries run on the unfused LDS-tile kernel (lds = 1, fuse = 0)",
+  if (any_analytic(c->meshes.data(), c->count) && !(v.fuse == 0 && (v.lds == 1 || (v.lds == 2 && d == 2))))
+    return why = "analytic boundaries run on the unfused LDS-tile kernel (lds = 1, fuse = 0) or, in 2D, the "
+                 "one-stage register march (lds = 2, fuse = 0)",
            PARAISO_ERR_UNSUPPORTED;
   if (first_order(c->meshes[0]) && v.lds != 1)
     return why = "first-order reconstruction runs on the LDS-tile kernels (lds = 1)", PARAISO_ERR_UNSUPPORTED;
@@ -528,7 +545,9 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   Launch L;
   if (v.lds == 3) L.fn = c->tab->resident1d;
   else if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
-  else if (v.lds == 2) L.fn = v.fuse ? c->tab->march_fused[ws] : c->tab->march_stage[ws];
+  else if (v.lds == 2)
+    L.fn = v.fuse ? c->tab->march_fused[ws]
+                  : (any_analytic(c->meshes.data(), c->count) ? c->tab->march_stage_an[ws] : c->tab->march_stage[ws]);
   else if (v.lds == 1) {
     const int opt = (any_analytic(c->meshes.data(), c->count) ? kOptAnalytic : 0) |
                     (first_order(c->meshes[0]) ? kOptFirstOrder : 0);
@@ -579,6 +598,11 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   c->lds = v.lds != 0;
   c->persistent = v.persistent != 0;
   c->resident = v.lds == 3;
+  c->ghosts = v.lds == 2 && d == 2 && any_analytic(c->meshes.data(), c->count);
+  c->ghost_blocks = 1;
+  for (const auto& m : c->meshes)
+    if (ghost_bytes(m))
+      c->ghost_blocks = std::max<int>(c->ghost_blocks, (2 * ghost_stride((int)m.n[0], (int)m.n[1]) + 255) / 256);
   c->nitems = nitems;
   c->geom = G;
   c->step = L;
@@ -619,6 +643,13 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
   lds_variant(d, v);
   if (any_analytic(meshes, count)) {
     v->fuse = 0;  // ghosts at each stage's own time
+    if (d == 2 && !first_order(meshes[0]) && march_offsets_fit(meshes, count)) {
+      // the one-stage register march with ghost arrays
+      v->lds = 2;
+      v->tile[0] = 64;
+      v->tile[1] = f64 ? 12 : 8;
+      v->threads = 256;
+    }
   } else if (first_order(meshes[0])) {
     // first-order reconstruction: the LDS-tile kernels only
   } else if (d == 1) {
@@ -732,6 +763,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   // host mesh table
   c->hm.resize(count);
   size_t u1off = L.u1;
+  size_t goff = L.ghost;
   int chunk = 0;
   for (int m = 0; m < count; ++m) {
     const paraiso_mesh& pm = meshes[m];
@@ -743,6 +775,8 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
     const size_t fbytes = align256((size_t)cells_of(pm) * c->esize);
     for (int q = 0; q < kMaxFields; ++q) M.w[q] = q < nf ? (void*)(c->ws + u1off + q * fbytes) : nullptr;
     u1off += nf * fbytes;
+    M.ghost = ghost_bytes(pm) ? (void*)(c->ws + goff) : nullptr;
+    goff += ghost_bytes(pm);
     double vol = 1.0;
     for (int a = 0; a < 3; ++a) {
       M.n[a] = (int)pm.n[a];

@@ -28,11 +28,12 @@ TUNED = {
     ("batch512", "f32"): dict(tile=(64, 32), lds=2, fuse=1, waves_per_eu=0, threads=256, persistent=1),
     # the whole advance in one launch, one workgroup holding the 1024 cells
     ("sod1024", "f64"): dict(tile=(1024,), lds=3, fuse=1),
-    # convergence tests with analytic boundaries, N <= 1024: the unfused LDS
-    # tile (the one family with exact-solution ghosts), from a tile x threads
-    # x hint sweep at 1024^2
-    ("convergence", "f32"): dict(tile=(64, 16), lds=1, fuse=0, waves_per_eu=0, threads=128),
-    ("convergence", "f64"): dict(tile=(32, 32), lds=1, fuse=0, waves_per_eu=0, threads=256),
+    # convergence tests with analytic boundaries, N <= 1024: the one-stage
+    # register march reading ghost arrays, from a rows x threads x hint sweep
+    # at 1024^2 (the unfused LDS tile, which evaluates the exact solution
+    # in its edge tiles, is 2.1x / 1.8x slower)
+    ("convergence", "f32"): dict(tile=(64, 8), lds=2, fuse=0, waves_per_eu=0, threads=256),
+    ("convergence", "f64"): dict(tile=(64, 12), lds=2, fuse=0, waves_per_eu=0, threads=256),
 }
 
 

@@ -24,6 +24,8 @@ pytestmark = pytest.mark.gpu
 A = pb.ANALYTIC
 KINDS = {"entropy": pb.ENTROPY_WAVE, "sound": pb.SOUND_WAVE, "sod": pb.SHOCK_TUBE}
 OBLIQUE = math.pi / 3
+# the one-stage register march, ghost cells from the ghost arrays
+MARCH = dict(tile=(64, 8), lds=2, fuse=0, threads=256)
 
 
 def _problem(kind, angle):
@@ -62,7 +64,7 @@ def _one_step(ndim, n, bc, dtype, an, t0, variant=None, nsteps=1):
 @pytest.mark.parametrize("angle", [0.0, OBLIQUE])
 def test_one_step_2d_matches_oracle(dtype, kind, angle):
     an = _problem(kind, angle)
-    for variant in (None, dict(tile=(16, 8), lds=1, fuse=0, persistent=1)):
+    for variant in (None, dict(tile=(16, 8), lds=1, fuse=0, persistent=1), MARCH, dict(MARCH, tile=(64, 4))):
         got, ref, _, _ = _one_step(2, (37, 29), (A, A), dtype, an, 0.07, variant)
         err = state_err(got, ref, 1.4)
         print(f"  {kind} angle {angle:.3f} {dtype} {variant}: {err:.3e}", flush=True)
@@ -84,16 +86,18 @@ def test_analytic_axis_mixes_with_periodic_and_outflow():
     # coaxial waves do not depend on y: the y axis may be periodic or outflow
     for bc in ((A, pb.PERIODIC), (A, pb.OUTFLOW), (pb.PERIODIC, A)):
         an = _problem("entropy", 0.0 if bc[0] == A else math.pi / 2)
-        got, ref, _, _ = _one_step(2, (33, 18), bc, "f64", an, 0.11)
-        assert state_err(got, ref, 1.4) <= 1e-12, bc
+        for variant in (None, MARCH):
+            got, ref, _, _ = _one_step(2, (33, 18), bc, "f64", an, 0.11, variant)
+            assert state_err(got, ref, 1.4) <= 1e-12, (bc, variant)
 
 
 def test_explicit_steps_carry_the_time():
     # three explicit steps: ghosts at t0 + k dt (and + dt/2 in stage 2); the
     # device time is the same sum of doubles as on the host
-    got, ref, tg, t = _one_step(2, (40, 24), (A, A), "f64", _problem("sod", OBLIQUE), 0.02, nsteps=3)
-    assert tg == t
-    assert state_err(got, ref, 1.4) <= 1e-12
+    for variant in (None, MARCH):
+        got, ref, tg, t = _one_step(2, (40, 24), (A, A), "f64", _problem("sod", OBLIQUE), 0.02, variant, nsteps=3)
+        assert tg == t
+        assert state_err(got, ref, 1.4) <= 1e-12
 
 
 def test_time_survives_cfl_and_variant_changes():
@@ -134,18 +138,19 @@ def test_advance_matches_oracle():
         m = oracle.Mesh(2, (40, 36), 1.4, (A, A))
         U0 = oracle.exact_state(m, an, 0.0)
         ref, t_ref, n_ref = oracle.advance(m, U0, 0.5, t_end, analytic=an)
-        s = _solver(2, (40, 36), (A, A), "f64", an)
-        s.upload(U0)
-        t, n = s.advance(t_end, 0.5)
-        got = gpu_state(s)
-        s.close()
-        assert t == [t_end] and n == [n_ref], kind
-        assert state_err(got, ref, 1.4) < 1e-11, kind
+        for variant in (None, MARCH):
+            s = _solver(2, (40, 36), (A, A), "f64", an, variant)
+            s.upload(U0)
+            t, n = s.advance(t_end, 0.5)
+            got = gpu_state(s)
+            s.close()
+            assert t == [t_end] and n == [n_ref], (kind, variant)
+            assert state_err(got, ref, 1.4) < 1e-11, (kind, variant)
 
 
-def _l1_gpu(kind, angle, n, t_end, dtype="f64"):
+def _l1_gpu(kind, angle, n, t_end, dtype="f64", variant=None):
     an = _problem(kind, angle)
-    s = _solver(2, (n, n), (A, A), dtype, an)
+    s = _solver(2, (n, n), (A, A), dtype, an, variant)
     s.fill_exact(0.0)
     t, _ = s.advance(t_end, 0.5)
     assert t == [t_end]
@@ -171,6 +176,8 @@ def test_convergence_study(kind, angle):
     sizes = (32, 64, 128, 256)
     errs = [_l1_gpu(kind, angle, n, t_end) for n in sizes]
     assert abs(errs[0] - want) <= 1e-8 * want, (errs[0], want)
+    march = _l1_gpu(kind, angle, 32, t_end, variant=MARCH)
+    assert abs(march - want) <= 1e-8 * want, (march, want)
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     print(f"  {kind} angle {angle:.3f}: L1 {errs} orders {orders}", flush=True)
     lo = 0.7 if kind == "sod" else 1.6
@@ -197,8 +204,8 @@ def test_analytic_errors():
         s.set_analytic(an.kind, mesh=1)
     assert ei.value.code == pb.ERR_INVALID_ARG
     s.set_analytic(an.kind)
-    assert s.variant()["lds"] == 1 and s.variant()["fuse"] == 0
-    for v in (dict(tile=(16, 8), lds=1, fuse=1), dict(tile=(64, 8), lds=2, fuse=0),
+    assert s.variant()["lds"] == 2 and s.variant()["fuse"] == 0     # the one-stage march
+    for v in (dict(tile=(16, 8), lds=1, fuse=1), dict(tile=(64, 8), lds=2, fuse=1),
               dict(tile=(16, 8), lds=0, fuse=0)):
         with pytest.raises(pb.ParaisoError) as ei:
             s.set_variant(v)
