@@ -132,6 +132,31 @@ def run_gpu(U, dtype: str, variant: dict, steps: int, warmup: int, specs=None, t
             "mass_energy_drift": drift}
 
 
+def repetitions(U, dtype: str, variant: dict, reps: int = 10, steps_each: int = 50, warmup: int = 500):
+    """Mean and sample standard deviation of cell-updates/s over `reps`
+    separately timed runs of `steps_each` device-dt steps (after a warm-up)."""
+    import statistics
+    import torch
+    from paper_1204_4779_amd import binding as pb
+    s = pb.Solver([pb.MeshSpec(2, (N, N), 1.4, (0, 0))], dtype)
+    s.set_variant(variant)
+    s.upload(U)
+    t, _ = s.advance(float("inf"), CFL, max_steps=warmup, t0=[0.0])
+    vals = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(s.stream)
+        t, _ = s.advance(float("inf"), CFL, max_steps=steps_each, t0=t)
+        b.record(s.stream)
+        torch.cuda.synchronize()
+        vals.append(N * N * steps_each / (a.elapsed_time(b) / 1e3))
+    s.close()
+    return {"reps": reps, "steps_each": steps_each, "mean": statistics.mean(vals), "std": statistics.stdev(vals),
+            "note": "each repetition is one paraiso_advance call (includes its initial CFL reduction and host sync)"}
+
+
 def cpu_baseline(U, budget_s: float = 12.0):
     import numpy as np
     import oracle
@@ -456,6 +481,8 @@ def main():
         ru32 = run_gpu(pr.U, "f32", UNTUNED, max(args.steps // 5, 10), min(args.warmup, 50))
         log(f"FP64 untuned {UNTUNED}")
         ru64 = run_gpu(pr.U, "f64", UNTUNED, max(args.steps // 5, 10), min(args.warmup, 50))
+        log("FP32 tuned: 10 repetitions of 50 steps")
+        extra["f32_tuned_repetitions"] = repetitions(pr.U, "f32", tuned32)
         for name, r, dt, var in (("f64_tuned", r64, "f64", TUNED["f64"]), ("f32_untuned", ru32, "f32", UNTUNED),
                                  ("f64_untuned", ru64, "f64", UNTUNED)):
             k = r["steps"][0]

@@ -327,13 +327,18 @@ int32_t paraiso_wave_prepare(const paraiso_wave* lines, int32_t count, void* wor
 
 /*
  * Advance the `count` lines prepared in `workspace` by `steps` steps each,
- * one workgroup per line, enqueued on `hip_stream` (asynchronous).  Each
- * line's energy array receives E after each of these steps (from index 0).
- * The energy sums are taken in a fixed order: results are bitwise
- * reproducible.  Errors: INVALID_ARG (null workspace, count < 1, steps < 0,
- * misaligned workspace), HIP.
+ * one workgroup per line, enqueued on `hip_stream` (asynchronous).
+ * `max_cells` is the largest n among the prepared lines: it selects the
+ * kernel's cells per thread (ceil(max_cells / 256), rounded up to 1, 2, 3,
+ * 4, 6, 8, 12 or 16); a line longer than that allows is left untouched.
+ * Each line's energy array receives E after each of these steps (from
+ * index 0).  The energy sums are taken in a fixed order: results are
+ * bitwise reproducible.  Errors: INVALID_ARG (null workspace, count < 1,
+ * steps < 0, max_cells outside [3, PARAISO_WAVE_MAX_CELLS], misaligned
+ * workspace), HIP.
  */
-int32_t paraiso_wave_run(const void* workspace, int32_t count, int64_t steps, void* hip_stream);
+int32_t paraiso_wave_run(const void* workspace, int32_t count, int64_t steps, int64_t max_cells,
+                         void* hip_stream);
 
 /* paraiso_wave_prepare, then paraiso_wave_run. */
 int32_t paraiso_wave_advance(const paraiso_wave* lines, int32_t count, int64_t steps, void* workspace,

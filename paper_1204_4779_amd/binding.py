@@ -128,7 +128,7 @@ def load(path: str | None = None):
         "paraiso_set_time": ([vp, dp], i32),
         "paraiso_wave_workspace_bytes": ([i32, ctypes.POINTER(szt)], i32),
         "paraiso_wave_prepare": ([ctypes.POINTER(paraiso_wave), i32, vp, szt, vp], i32),
-        "paraiso_wave_run": ([vp, i32, i64, vp], i32),
+        "paraiso_wave_run": ([vp, i32, i64, i64, vp], i32),
         "paraiso_wave_advance": ([ctypes.POINTER(paraiso_wave), i32, i64, vp, szt, vp], i32),
         "paraiso_get_time": ([vp, dp], i32),
         "paraiso_destroy": ([vp], i32),
@@ -254,8 +254,8 @@ def paraiso_wave_prepare(lines, workspace_ptr: int, workspace_bytes: int, stream
                                        ctypes.c_void_p(stream_ptr)))
 
 
-def paraiso_wave_run(workspace_ptr: int, count: int, steps: int, stream_ptr: int) -> None:
-    _check(load().paraiso_wave_run(ctypes.c_void_p(workspace_ptr), int(count), int(steps),
+def paraiso_wave_run(workspace_ptr: int, count: int, steps: int, max_cells: int, stream_ptr: int) -> None:
+    _check(load().paraiso_wave_run(ctypes.c_void_p(workspace_ptr), int(count), int(steps), int(max_cells),
                                    ctypes.c_void_p(stream_ptr)))
 
 
@@ -472,7 +472,8 @@ class WaveLines:
     def run(self, steps: int):
         if self.recording and steps > self.capacity:
             raise ValueError("more steps than the energy buffers hold")
-        paraiso_wave_run(self.ws_ptr, len(self.f), steps, self.torch.cuda.current_stream(self.device).cuda_stream)
+        paraiso_wave_run(self.ws_ptr, len(self.f), steps, max(x.numel() for x in self.f),
+                         self.torch.cuda.current_stream(self.device).cuda_stream)
 
     def _lines(self, record_energy: bool):
         lines = []

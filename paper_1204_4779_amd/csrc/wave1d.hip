@@ -6,7 +6,8 @@
 //   E^{n+1} = sum_i (c^2 ((f^{n+1}[i+1] - f^{n+1}[i-1]) / 2dx)^2 + ((g^n[i] + g^{n+1}[i]) / 2)^2) dx / 2.
 //
 // One workgroup runs all steps of one line.  Thread t holds the R = ceil(n /
-// 256) consecutive cells [tR, tR + R) in registers, so all but the two end
+// 256) consecutive cells [tR, tR + R) in registers (the kernel is
+// instantiated for R up to 1, 2, 3, 4, 6, 8, 12 and 16), so all but the two end
 // cells find their neighbours in registers; the end values of every thread
 // go through LDS (double-buffered by step parity), which costs one barrier
 // per step.  The energy is summed in FP64 in a fixed order (per thread in
@@ -27,7 +28,6 @@ void paraiso_set_error(const std::string& msg);
 namespace {
 
 constexpr int kWaveThreads = 256;
-constexpr int kWaveSlots = PARAISO_WAVE_MAX_CELLS / kWaveThreads;  // cells per thread
 
 struct WaveDev {
   int n;
@@ -48,34 +48,61 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// One step of the cells a thread holds (cnt <= R of them; FULL: cnt == R,
+// no per-cell predicates).  f holds f^{n+1} on entry; returns the thread's
+// energy sum, in cell order, two interleaved accumulators.
+template <int R, bool FULL>
+__device__ __forceinline__ double wave_cells(const WaveDev& P, double* f, double* g, int cnt, double left_end,
+                                             double right_end) {
+  double e0 = 0.0, e1 = 0.0;
+  double fl = left_end;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (FULL || r < cnt) {
+      const double fr = (FULL ? r + 1 < R : r + 1 < cnt) ? f[r + 1 < R ? r + 1 : r] : right_end;
+      const double g1 = g[r] + P.k * (fr + fl - 2.0 * f[r]);
+      const double dfdx = (fr - fl) * P.inv2dx;
+      const double gm = (g[r] + g1) * 0.5;
+      const double term = (P.c2 * dfdx * dfdx + gm * gm) * P.half_dx;
+      if (r & 1) e1 += term; else e0 += term;
+      g[r] = g1;
+      fl = f[r];
+    }
+  }
+  return e0 + e1;
+}
+
+template <int R>
 __global__ void __launch_bounds__(kWaveThreads) k_wave1d(const WaveDev* probs, long long steps) {
   __shared__ double sFirst[2][kWaveThreads], sLast[2][kWaveThreads];
   __shared__ double sPart[2][kWaveThreads / 64];
   const WaveDev P = probs[blockIdx.x];
   const int tid = threadIdx.x;
   const int n = P.n;
-  const int R = (n + kWaveThreads - 1) / kWaveThreads;  // cells per thread, <= kWaveSlots
-  const int active = (n + R - 1) / R;                    // threads holding cells
-  const int i0 = tid * R;
-  const int cnt = tid < active ? min(R, n - i0) : 0;
+  if (n > R * kWaveThreads) return;                      // a line longer than the launch allows: untouched
+  const int Rl = (n + kWaveThreads - 1) / kWaveThreads;  // cells per thread of this line, <= R
+  const int active = (n + Rl - 1) / Rl;                  // threads holding cells
+  const int i0 = tid * Rl;
+  const int cnt = tid < active ? min(Rl, n - i0) : 0;
   const int prev = tid == 0 ? active - 1 : tid - 1;      // holder of cell i0 - 1 (periodic)
   const int next = tid == active - 1 ? 0 : tid + 1;      // holder of cell i0 + cnt
-  double f[kWaveSlots], g[kWaveSlots];
+  const bool full = cnt == R;
+  double f[R], g[R];
 #pragma unroll
-  for (int r = 0; r < kWaveSlots; ++r) {
+  for (int r = 0; r < R; ++r) {
     f[r] = r < cnt ? P.f[i0 + r] : 0.0;
     g[r] = r < cnt ? P.g[i0 + r] : 0.0;
   }
   for (long long s = 0; s < steps; ++s) {
     const int b = (int)(s & 1);
 #pragma unroll
-    for (int r = 0; r < kWaveSlots; ++r)
+    for (int r = 0; r < R; ++r)
       if (r < cnt) f[r] = f[r] + P.dt * g[r];
     if (cnt > 0) {
       sFirst[b][tid] = f[0];
       double last = f[0];
 #pragma unroll
-      for (int r = 1; r < kWaveSlots; ++r)
+      for (int r = 1; r < R; ++r)
         if (r == cnt - 1) last = f[r];
       sLast[b][tid] = last;
     }
@@ -90,19 +117,8 @@ __global__ void __launch_bounds__(kWaveThreads) k_wave1d(const WaveDev* probs, l
     if (cnt > 0) {
       const double left_end = sLast[b][prev];
       const double right_end = sFirst[b][next];
-      double fl = left_end;
-#pragma unroll
-      for (int r = 0; r < kWaveSlots; ++r) {
-        if (r < cnt) {
-          const double fr = r + 1 < cnt ? f[r + 1 < kWaveSlots ? r + 1 : r] : right_end;
-          const double g1 = g[r] + P.k * (fr + fl - 2.0 * f[r]);
-          const double dfdx = (fr - fl) * P.inv2dx;
-          const double gm = (g[r] + g1) * 0.5;
-          e += (P.c2 * dfdx * dfdx + gm * gm) * P.half_dx;
-          g[r] = g1;
-          fl = f[r];
-        }
-      }
+      e = full ? wave_cells<R, true>(P, f, g, cnt, left_end, right_end)
+               : wave_cells<R, false>(P, f, g, cnt, left_end, right_end);
     }
     e = wave_sum(e);
     if ((tid & 63) == 0) sPart[b][tid >> 6] = e;
@@ -115,12 +131,28 @@ __global__ void __launch_bounds__(kWaveThreads) k_wave1d(const WaveDev* probs, l
     P.energy[steps - 1] = tot;
   }
 #pragma unroll
-  for (int r = 0; r < kWaveSlots; ++r) {
+  for (int r = 0; r < R; ++r) {
     if (r < cnt) {
       P.f[i0 + r] = f[r];
       P.g[i0 + r] = g[r];
     }
   }
+}
+
+// Cells per thread of the instantiated kernels, and the kernel for a launch
+// whose longest line has max_cells cells.
+constexpr int kWaveR[] = {1, 2, 3, 4, 6, 8, 12, 16};
+
+const void* wave_kernel(int64_t max_cells) {
+  const int need = (int)((max_cells + kWaveThreads - 1) / kWaveThreads);
+  if (need <= 1) return (const void*)k_wave1d<1>;
+  if (need <= 2) return (const void*)k_wave1d<2>;
+  if (need <= 3) return (const void*)k_wave1d<3>;
+  if (need <= 4) return (const void*)k_wave1d<4>;
+  if (need <= 6) return (const void*)k_wave1d<6>;
+  if (need <= 8) return (const void*)k_wave1d<8>;
+  if (need <= 12) return (const void*)k_wave1d<12>;
+  return (const void*)k_wave1d<16>;
 }
 
 int wave_fail(int code, const std::string& msg) {
@@ -192,14 +224,19 @@ int32_t paraiso_wave_prepare(const paraiso_wave* probs, int32_t count, void* wor
   return PARAISO_OK;
 }
 
-int32_t paraiso_wave_run(const void* workspace, int32_t count, int64_t steps, void* hip_stream) {
+int32_t paraiso_wave_run(const void* workspace, int32_t count, int64_t steps, int64_t max_cells, void* hip_stream) {
   if (!workspace) return wave_fail(PARAISO_ERR_INVALID_ARG, "null workspace");
   if (count < 1) return wave_fail(PARAISO_ERR_INVALID_ARG, "count must be >= 1");
   if (steps < 0) return wave_fail(PARAISO_ERR_INVALID_ARG, "steps must be >= 0");
+  if (max_cells < 3 || max_cells > PARAISO_WAVE_MAX_CELLS)
+    return wave_fail(PARAISO_ERR_INVALID_ARG, "max_cells must be in [3, " + std::to_string(PARAISO_WAVE_MAX_CELLS) + "]");
   if ((uintptr_t)workspace % 256) return wave_fail(PARAISO_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
-  hipLaunchKernelGGL(k_wave1d, dim3(count), dim3(kWaveThreads), 0, (hipStream_t)hip_stream,
-                     (const WaveDev*)workspace, (long long)steps);
-  hipError_t e = hipGetLastError();
+  const WaveDev* table = (const WaveDev*)workspace;
+  long long st = (long long)steps;
+  void* args[] = {(void*)&table, (void*)&st};
+  hipError_t e = hipLaunchKernel(wave_kernel(max_cells), dim3(count), dim3(kWaveThreads), args, 0,
+                                 (hipStream_t)hip_stream);
+  if (e == hipSuccess) e = hipGetLastError();
   if (e != hipSuccess) return wave_fail(PARAISO_ERR_HIP, std::string("k_wave1d: ") + hipGetErrorString(e));
   return PARAISO_OK;
 }
@@ -209,7 +246,9 @@ int32_t paraiso_wave_advance(const paraiso_wave* probs, int32_t count, int64_t s
   if (steps < 0) return wave_fail(PARAISO_ERR_INVALID_ARG, "steps must be >= 0");
   int32_t rc = paraiso_wave_prepare(probs, count, workspace, workspace_bytes, hip_stream);
   if (rc) return rc;
-  return paraiso_wave_run(workspace, count, steps, hip_stream);
+  int64_t max_cells = 3;
+  for (int m = 0; m < count; ++m) max_cells = probs[m].n > max_cells ? probs[m].n : max_cells;
+  return paraiso_wave_run(workspace, count, steps, max_cells, hip_stream);
 }
 
 }  // extern "C"

@@ -203,3 +203,7 @@ def test_wave_entry_points_validate_before_any_device_work(lib):
     with pytest.raises(pb.ParaisoError) as ei:
         pb.paraiso_wave_advance([line()] * 8, 1, ws, 256, 0)
     assert ei.value.code == pb.ERR_WORKSPACE
+    for args in ((ws, 1, 1, 2), (ws, 1, 1, 4097), (ws, 0, 1, 64), (ws, 1, -1, 64), (ws + 8, 1, 1, 64)):
+        with pytest.raises(pb.ParaisoError) as ei:
+            pb.paraiso_wave_run(*args, 0)
+        assert ei.value.code == pb.ERR_INVALID_ARG, args

@@ -107,3 +107,19 @@ def test_zero_steps_and_errors():
     with pytest.raises(pb.ParaisoError) as ei:
         big.advance(1)
     assert ei.value.code == pb.ERR_INVALID_ARG and "line 0" in str(ei.value)
+
+
+def test_lines_longer_than_the_launch_allows_are_untouched():
+    import torch
+    rng = np.random.default_rng(9)
+    fs = [rng.normal(size=100), rng.normal(size=600)]
+    gs = [rng.normal(size=100), rng.normal(size=600)]
+    w = pb.WaveLines(fs, gs, 1.0, 0.1, 0.05, 3)
+    w.prepare()
+    pb.paraiso_wave_run(w.ws_ptr, 2, 3, 256, torch.cuda.current_stream().cuda_stream)   # one cell per thread
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(w.f[1].cpu().numpy(), fs[1])
+    np.testing.assert_array_equal(w.g[1].cpu().numpy(), gs[1])
+    fr, gr, er = wave.advance(fs[0], gs[0], 1.0, 0.1, 0.05, 3)
+    np.testing.assert_allclose(w.g[0].cpu().numpy(), gr, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(w.energy[0].cpu().numpy()[:3], er, rtol=1e-13)
