@@ -320,7 +320,7 @@ class Solver:
     """One context over one mesh or a batch; state buffers are torch tensors of shape
     (d+2, nz, ny, nx) (leading axes dropped for d < 3), two per mesh."""
 
-    def __init__(self, specs, dtype: str = "f32", device=None, stream=None):
+    def __init__(self, specs, dtype: str = "f32", device=None, stream=None, workspace_fill: int | None = None):
         import torch
         self.torch = torch
         if isinstance(specs, MeshSpec):
@@ -363,7 +363,10 @@ class Solver:
             meshes.append(m)
         self.meshes = meshes
         self.ws_bytes = paraiso_workspace_bytes(meshes)
-        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        if workspace_fill is None:
+            self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        else:   # a byte pattern in the whole workspace (tests: reads of unwritten workspace show)
+            self.workspace = torch.full((self.ws_bytes + 256,), int(workspace_fill), dtype=torch.uint8, device=dev)
         base = self.workspace.data_ptr()
         self.ws_ptr = (base + 255) & ~255
         if stream is None:
