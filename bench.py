@@ -440,6 +440,8 @@ def main():
                     help="convergence workload: mesh sizes N (default 16 32 ... 1024)")
     ap.add_argument("--prof", action="store_true",
                     help="profiling run: headline only, plus a 512 MiB device copy that calibrates HBM counters")
+    ap.add_argument("--prof-fp64", action="store_true",
+                    help="with --prof: run the FP64 tuned KH variant instead of the FP32 headline")
     args = ap.parse_args()
     if args.prof:
         args.no_cpu = args.no_extra = True
@@ -465,6 +467,12 @@ def main():
     log("generating KH 2048^2 input")
     pr = inputs.kelvin_helmholtz_2d(N, seed=1204)
     cells = N * N
+    if args.prof and args.prof_fp64:
+        r = run_gpu(pr.U, "f64", TUNED["f64"], args.steps, args.warmup)
+        calibration_copy()
+        print(json.dumps({"profiled": "kh2048 f64 tuned", "variant": TUNED["f64"], "steps": args.steps,
+                          "ms_per_step": r["event_ms"] / args.steps}))
+        return
 
     tuned32 = json.loads(args.variant) if args.variant else TUNED["f32"]
     log(f"FP32 tuned {tuned32}")
