@@ -225,3 +225,27 @@ def test_analytic_errors():
         q.set_analytic(pb.ENTROPY_WAVE, angle=0.5)
     assert ei.value.code == pb.ERR_INVALID_ARG
     q.close()
+
+
+@pytest.mark.parametrize("variant", [dict(MARCH, persistent=1), dict(tile=(16, 8), lds=1, fuse=0, persistent=1)])
+def test_batch_of_analytic_problems_equals_solo_runs(variant):
+    # uneven meshes, each with its own problem, in one persistent launch per stage
+    probs = [("entropy", OBLIQUE, (40, 36)), ("sod", 0.0, (64, 20)), ("sound", OBLIQUE, (33, 47))]
+    specs = [pb.MeshSpec(2, n, 1.4, (A, A)) for _, _, n in probs]
+    b = pb.Solver(specs, "f64")
+    for k, (kind, angle, _) in enumerate(probs):
+        an = _problem(kind, angle)
+        b.set_analytic(an.kind, an.angle, an.amplitude, mesh=k)
+        b.fill_exact(0.0, mesh=k)
+    b.set_variant(variant)
+    t, n = b.advance(0.03, 0.5, t0=[0.0] * 3)
+    assert t == [0.03] * 3
+    for k, (kind, angle, size) in enumerate(probs):
+        an = _problem(kind, angle)
+        s = _solver(2, size, (A, A), "f64", an, dict(variant, persistent=0))
+        s.fill_exact(0.0)
+        ts, ns = s.advance(0.03, 0.5)
+        assert ns[0] == n[k]
+        np.testing.assert_array_equal(gpu_state(b, k), gpu_state(s))
+        s.close()
+    b.close()
