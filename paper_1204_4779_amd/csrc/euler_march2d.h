@@ -37,24 +37,29 @@ __host__ __device__ constexpr int march2d_item_rows(int nwaves, int rows) {
   return nwaves * rows - (march2d_shares(nwaves, rows) ? 2 : 0);
 }
 
+// Wave shifts by one lane.  The edge lane that has no source gets 0 from
+// the DPP bound control, not from the old operand: with old ignored the
+// compiler neither zeroes a destination register before each DPP move
+// (one v_mov per 32-bit half, 64 per row push in FP64) nor loses the
+// folding of FP32 shifts into their consumer (v_sub_f32_dpp).
 // lane l receives lane l-1 (lane 0 receives 0)
 __device__ __forceinline__ float lane_from_left(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x138, 0xf, 0xf, true));
 }
 // lane l receives lane l+1 (lane 63 receives 0)
 __device__ __forceinline__ float lane_from_right(float x) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), 0x130, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_from_left(double x) {
   const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x138, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x138, 0xf, 0xf, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double lane_from_right(double x) {
   const long long b = __builtin_bit_cast(long long, x);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, false);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x130, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x130, 0xf, 0xf, true);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
