@@ -41,3 +41,14 @@ def test_kernel_name_follows_the_variant():
     assert bench.kernel_name(dict(tile=(64, 20), lds=2, fuse=1, waves_per_eu=0)) == "k_march2d<float,0,true>"
     assert bench.kernel_name(dict(tile=(64, 16), lds=2, fuse=0, waves_per_eu=4)) == "k_march2d<float,4,false>"
     assert bench.kernel_name(dict(tile=(32, 16), lds=1, fuse=1)) == "k_fused_lds<float,2,0>"
+
+
+def test_traffic_constant_is_the_one_its_profile_records():
+    # bench.py reports the measured HBM bytes only for the kernel sources and
+    # variant they were counted on; the committed profile of that kernel must
+    # name the same sources and bytes
+    text = open(os.path.join(ROOT, "profiles", "k_march2d_f32_kh2048.md")).read()
+    assert f"`{bench.TRAFFIC['sources']}`" in text
+    assert f"Measured {bench.TRAFFIC['bytes_per_launch'] / 1e6:.1f} MB per launch" in text
+    v = bench.TRAFFIC["variant"]
+    assert f"tile ({v['tile'][0]}, {v['tile'][1]})" in text and f"{v['threads']} threads" in text
