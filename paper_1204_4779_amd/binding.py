@@ -339,7 +339,10 @@ class Solver:
             dims = tuple(reversed(n[: sp.ndim]))
             cells = n[0] * n[1] * n[2]
             padded = (cells + 63) // 64 * 64      # every field starts 256-byte aligned
-            strides = (padded,) + tuple(int(v) for v in torch.empty(dims).stride())
+            inner = [1]                           # contiguous strides of one field, x fastest
+            for extent in reversed(dims[1:]):
+                inner.insert(0, inner[0] * extent)
+            strides = (padded,) + tuple(inner)
             pair = []
             for _ in range(2):
                 store = torch.zeros((self.nf, padded), dtype=tdt, device=dev)
