@@ -468,6 +468,7 @@ class WaveLines:
         self.ws_bytes = paraiso_wave_workspace_bytes(count)
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         self.ws_ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.recording = None   # set by prepare()
 
     def prepare(self, record_energy: bool = True):
         """Upload the line table; run() then enqueues steps without host work."""
@@ -476,6 +477,8 @@ class WaveLines:
         self.recording = record_energy
 
     def run(self, steps: int):
+        if self.recording is None:
+            raise RuntimeError("WaveLines.run: call prepare() first (it uploads the line table)")
         if self.recording and steps > self.capacity:
             raise ValueError("more steps than the energy buffers hold")
         paraiso_wave_run(self.ws_ptr, len(self.f), steps, max(x.numel() for x in self.f),

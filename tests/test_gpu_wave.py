@@ -103,6 +103,8 @@ def test_zero_steps_and_errors():
     w = pb.WaveLines([f0], [g0], C, dx, dt, 4)
     with pytest.raises(ValueError):
         w.advance(5)
+    with pytest.raises(RuntimeError):   # run() before prepare(): no line table on the device yet
+        w.run(1)
     big = pb.WaveLines([np.zeros(4097)], [np.zeros(4097)], C, dx, dt, 1)
     with pytest.raises(pb.ParaisoError) as ei:
         big.advance(1)
