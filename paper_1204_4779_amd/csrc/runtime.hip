@@ -647,8 +647,11 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
       // the one-stage register march with ghost arrays
       v->lds = 2;
       v->tile[0] = 64;
-      v->tile[1] = f64 ? 12 : 8;
+      v->tile[1] = 8;
       v->threads = 256;
+      // FP64: 173 VGPRs uncapped (2 waves per SIMD); capped at 168 the kernel
+      // runs 3, which also lets a 1024^2 mesh's 576 blocks be resident at once
+      if (f64) v->waves_per_eu = 3;
     }
   } else if (first_order(meshes[0])) {
     // first-order reconstruction: the LDS-tile kernels only

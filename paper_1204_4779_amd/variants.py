@@ -31,9 +31,11 @@ TUNED = {
     # convergence tests with analytic boundaries, N <= 1024: the one-stage
     # register march reading ghost arrays, from a rows x threads x hint sweep
     # at 1024^2 (the unfused LDS tile, which evaluates the exact solution
-    # in its edge tiles, is 2.1x / 1.8x slower)
+    # in its edge tiles, is 2.1x / 1.8x slower); FP64 with the 3-waves hint
+    # (168 VGPRs instead of 173: 3 waves per SIMD, 16.2 against 15.7 G for the
+    # best uncapped variant, 12 rows)
     ("convergence", "f32"): dict(tile=(64, 8), lds=2, fuse=0, waves_per_eu=0, threads=256),
-    ("convergence", "f64"): dict(tile=(64, 12), lds=2, fuse=0, waves_per_eu=0, threads=256),
+    ("convergence", "f64"): dict(tile=(64, 8), lds=2, fuse=0, waves_per_eu=3, threads=256),
 }
 
 

@@ -135,7 +135,8 @@ def test_default_variant(lib):
         assert (v.lds, v.fuse) == ((2, 0) if d == 2 else (1, 0)), d
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, pb.ANALYTIC, 0))])
     assert (v.lds, v.fuse, v.persistent, tuple(v.tile)) == (2, 0, 1, (64, 8, 1))
-    assert tuple(pb.paraiso_default_variant([_mesh(dtype=pb.F64, bc=(pb.ANALYTIC,) * 3)]).tile) == (64, 12, 1)
+    v = pb.paraiso_default_variant([_mesh(dtype=pb.F64, bc=(pb.ANALYTIC,) * 3)])
+    assert (tuple(v.tile), v.waves_per_eu) == ((64, 8, 1), 3)   # FP64: capped at 3 waves per SIMD
     # first-order reconstruction: the LDS-tile kernels (fused unless analytic)
     for d, n in ((1, (64, 1, 1)), (2, (8, 8, 1)), (3, (4, 4, 4))):
         v = pb.paraiso_default_variant([_mesh(d, n, order=1)])
