@@ -249,10 +249,13 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
 }
 
 // CFL quantity sum_a (|v_a| + c)/dx_a of one cell, in FP64; returns a
-// negative value for a non-physical or non-finite state.  With rho > 0,
-// every other failure (p <= 0, a NaN or infinite component) makes q NaN on
-// its way through the reciprocal square root of gamma p rho, so one test
-// for rho > 0 and one for q < inf cover them all.
+// negative value for a non-physical or non-finite state.  Evaluated as
+// (sum_a (|m_a| + rho c)/dx_a) / rho with (rho c)^2 = gamma rho p and
+// rho p = (gamma - 1)(rho E - |m|^2/2), so the reciprocal of rho and the
+// reciprocal square root of gamma rho p are independent chains.  With
+// rho > 0, every other failure (p <= 0, a NaN or infinite component) makes
+// q NaN on its way through that reciprocal square root, so one test for
+// rho > 0 and one for q < inf cover them all.
 template <typename T, int D>
 __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double gamma) {
   double ud[D + 2];
@@ -260,18 +263,15 @@ __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double
   for (int q = 0; q < D + 2; ++q) ud[q] = (double)u[q];
   const double rho = ud[0];
   const double ir = Fp<double>::rcp(rho);
-  double ke = 0.0;
-  double vel[D];
+  double m2 = 0.0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) {
-    vel[a] = ud[1 + a] * ir;
-    ke += vel[a] * ud[1 + a];
-  }
-  const double p = (gamma - 1.0) * (ud[D + 1] - 0.5 * ke);
-  const double cs = Fp<double>::sqrt_ratio(gamma * p, rho);
+  for (int a = 0; a < D; ++a) m2 = fma(ud[1 + a], ud[1 + a], m2);
+  const double grp = gamma * (gamma - 1.0) * fma(rho, ud[D + 1], -0.5 * m2);  // gamma rho p
+  const double rc = grp * Fp<double>::rsqrt(grp);                            // rho c
   double q = 0.0;
 #pragma unroll
-  for (int a = 0; a < D; ++a) q += (fabs(vel[a]) + cs) * inv_dx[a];
+  for (int a = 0; a < D; ++a) q = fma(fabs(ud[1 + a]) + rc, inv_dx[a], q);
+  q *= ir;
   const bool ok = (rho > 0.0) && (q < __builtin_huge_val());
   return ok ? q : -1.0;
 }
