@@ -122,6 +122,32 @@ def test_cfl_flags_nonphysical():
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_cfl_flags_nonpositive_pressure(dtype, ndim):
+    # p < 0 (kinetic energy above the total) and p = 0 exactly (at rest, E = 0)
+    # in one cell: the oracle's failure cases, which the GPU's CFL term must
+    # report too (its sound speed goes through the reciprocal square root of
+    # gamma rho p)
+    pr = inputs.random_state(ndim, SHAPES[ndim], seed=29)
+    cell = (1,) * ndim
+    for make in ("negative", "zero"):
+        bad = pr.U.copy()
+        if make == "negative":
+            m2 = sum(bad[(1 + a,) + cell] ** 2 for a in range(ndim))
+            bad[(ndim + 1,) + cell] = 0.25 * m2 / bad[(0,) + cell]
+        else:
+            for a in range(ndim):
+                bad[(1 + a,) + cell] = 0.0
+            bad[(ndim + 1,) + cell] = 0.0
+        with pytest.raises(FloatingPointError):
+            oracle.cfl_dt(oracle_mesh(pr), as_input(bad, dtype), 0.5)
+        s = gpu_solver(spec_of(pr), dtype, None, bad)
+        with pytest.raises(FloatingPointError):
+            s.cfl_dt(0.5)
+        s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 def test_totals_match_oracle(dtype, ndim):
     pr = inputs.random_state(ndim, SHAPES[ndim], seed=23)
