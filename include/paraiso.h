@@ -184,6 +184,14 @@ int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, parai
  * CFL time step of the current state of every mesh:
  * dt_out[m] = cfl / max_i sum_a (|v_a| + c)/dx_a, computed in FP64 whatever
  * the state's element type.  Synchronous.  0 < cfl <= 1.
+ * Defined by: the time step of the two-stage marching is set by the CFL
+ * condition (section "Tuning Experiments / The Target Program", the sentence
+ * before the time-marching equations; the paper does not print the formula,
+ * this is the reading every kernel and the oracle share), taken over the mesh
+ * as the Orthotope Machine's Reduce with the Min operator (section "Outline of
+ * The Orthotope Machine", paragraph Reduce): a global value folded from every
+ * cell's local value; here the maximum of the signal-speed term, whose
+ * reciprocal is the minimum time step.
  * Errors: INVALID_ARG, NONFINITE (any cell with rho <= 0, p <= 0 or a
  * non-finite value; dt_out is then unspecified), HIP.
  */
@@ -191,7 +199,12 @@ int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
 
 /*
  * One midpoint-RK2 step of every mesh with the caller's time steps
- * dt[m] >= 0 (finite).  Reads the current buffer, writes the other one and
+ * dt[m] >= 0 (finite): F0 = Flux(U0), U1 = AddFlux(dt/2, F0, U0),
+ * F1 = Flux(U1), U2 = AddFlux(dt, F1, U0) (section "Tuning Experiments / The
+ * Target Program", the time-marching equations and the AddFlux equation).  It
+ * is the generated solver class's proceed() of the paper (section "Tuning
+ * Targets", the generated code listing): a call that advances the class's
+ * static state arrays in place; here the state moves between the two buffers.  Reads the current buffer, writes the other one and
  * makes it current; the device-held time advances by dt[m].  Asynchronous
  * on the context's stream.
  * Errors: INVALID_ARG (also: an analytic mesh without a problem set), HIP.
@@ -201,12 +214,18 @@ int32_t paraiso_step(paraiso_ctx* ctx, const double* dt);
 /*
  * Advance every mesh from t_inout[m] towards t_end with dt = CFL step
  * clamped so that no step passes t_end, for at most max_steps steps per
- * mesh.  The time step, the time and the step count stay on the device;
+ * mesh: repeated proceed() calls of the generated class (section "Tuning
+ * Targets") with the time step of each from the CFL reduction of its input
+ * (paraiso_cfl_dt), as the target program's time marching prescribes
+ * (section "Tuning Experiments / The Target Program").  The time step, the time and the step count stay on the device;
  * step sequences are replayed from captured HIP graphs.  On return
  * t_inout[m] and steps_out[m] hold each mesh's time and steps taken.
  * Synchronous.  0 < cfl <= 1, max_steps >= 0, t_end finite.
- * Errors: INVALID_ARG, NONFINITE (the state became non-physical; the
- * state buffers then hold the offending step's output), HIP.
+ * Errors: INVALID_ARG, NONFINITE (a mesh's state became non-physical, as
+ * the CFL reduction of each new state detects: that mesh takes no further
+ * step, its current buffer holds the offending step's output and
+ * t_inout[m] and steps_out[m] that step's time and count; the other meshes
+ * of a batch have advanced to where the call stopped), HIP.
  */
 int32_t paraiso_advance(paraiso_ctx* ctx, double t_end, double cfl, int64_t max_steps,
                         double* t_inout, int64_t* steps_out);
@@ -278,6 +297,12 @@ int32_t paraiso_current(const paraiso_ctx* ctx, int32_t* idx);
  * Conserved totals of the current state: out[m*(ndim+2) + q] = cell volume
  * times the sum over cells of field q of mesh m, accumulated in FP64 in a
  * fixed order (bitwise reproducible for a given variant).  Synchronous.
+ * Defined by: the Reduce of the Orthotope Machine with the Sum operator
+ * (section "Outline of The Orthotope Machine", paragraph Reduce), which the
+ * paper's linear-wave example applies to audit its discrete energy (section
+ * "An Example of Orthotope Machine Data-Flow Graph"); here the audited
+ * quantities are the conserved mass, momenta and energy of the Euler state.
+ * Errors: INVALID_ARG (null pointer), HIP.
  */
 int32_t paraiso_totals(paraiso_ctx* ctx, double* out);
 

@@ -206,9 +206,17 @@ def paraiso_step(ctx: int, dts) -> None:
 
 
 def paraiso_advance(ctx: int, t_end: float, cfl: float, max_steps: int, t0s) -> tuple:
+    """(t, steps) per mesh.  A non-physical state raises NonFiniteError whose
+    `t` and `steps` hold each mesh's time and step count at return (the
+    failing mesh's: those of the step that produced the state)."""
     t = _dbl_array(t0s)
     steps = (ctypes.c_int64 * len(t0s))()
-    _check(load().paraiso_advance(ctypes.c_void_p(ctx), float(t_end), float(cfl), int(max_steps), t, steps))
+    rc = load().paraiso_advance(ctypes.c_void_p(ctx), float(t_end), float(cfl), int(max_steps), t, steps)
+    try:
+        _check(rc)
+    except NonFiniteError as e:
+        e.t, e.steps = list(t), list(steps)
+        raise
     return list(t), list(steps)
 
 

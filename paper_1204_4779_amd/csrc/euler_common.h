@@ -14,7 +14,10 @@
 // t and the step count and clears slot (n+2)%3 of the maximum, and every
 // block folds its cells' CFL terms of the new state into slot (n+1)%3 with an
 // integer atomic max on the FP64 bit pattern (positive doubles order like
-// their bits).  No grid barrier is needed.
+// their bits).  A 3-slot ring of non-physical flags follows the same rule:
+// the CFL epilogue flags slot (n+1)%3, and a step whose slot n%3 is flagged
+// does not advance (the offending state, its time and its step count stay).
+// No grid barrier is needed.
 #pragma once
 
 #include "euler_device.h"
@@ -63,7 +66,7 @@ struct Ctl {
   double t[3];
   unsigned long long qbits[3];
   long long steps[3];
-  int flags;  // bit 0: non-physical or non-finite state seen
+  int flags[3];  // per ring slot: bit 0 set when the state of that slot is non-physical or non-finite
   int pad_;
 };
 
@@ -168,8 +171,11 @@ __device__ __forceinline__ Tile tile_of(const Args& a, int item) {
   return t;
 }
 
-// dt of mesh m for this step; `active` false once t >= t_end or the step
-// budget is spent (the step then copies U0 to the output).
+// dt of mesh m for this step; `active` false once t >= t_end, the step
+// budget is spent or the input state was found non-physical (the step then
+// copies U0 to the output, and time and step count stay).  The flag is read
+// from this step's ring slot, which no block of this launch writes, so every
+// block of a launch takes the same decision.
 __device__ __forceinline__ double step_dt(const Args& a, int m, bool& active) {
   if (a.dt) {
     active = true;
@@ -178,7 +184,7 @@ __device__ __forceinline__ double step_dt(const Args& a, int m, bool& active) {
   const Ctl& c = a.ctl[m];
   const double t = c.t[a.ring];
   const long long st = c.steps[a.ring];
-  active = (t < a.prm->t_end) && (st < a.prm->max_steps);
+  active = (t < a.prm->t_end) && (st < a.prm->max_steps) && c.flags[a.ring] == 0;
   if (!active) return 0.0;
   double dt = a.prm->cfl / __longlong_as_double((long long)c.qbits[a.ring]);
   if (dt > a.prm->t_end - t) dt = a.prm->t_end - t;
@@ -194,6 +200,10 @@ __device__ __forceinline__ void step_bookkeeping(const Args& a, int m, double dt
   c.t[nx] = active ? c.t[a.ring] + dt : c.t[a.ring];
   c.steps[nx] = c.steps[a.ring] + (active ? 1 : 0);
   if (!a.dt) c.qbits[nn] = 0ull;
+  // an inactive step copies its input, so its output keeps the input's flag;
+  // an active step's CFL epilogue sets slot nx itself (cleared a step ago)
+  if (!active) c.flags[nx] = c.flags[a.ring];
+  c.flags[nn] = 0;
   if (m == 0 && a.queue) {
 #pragma unroll
     for (int k = 0; k < 16; ++k) a.queue[nn * 16 + k] = 0u;
@@ -221,7 +231,7 @@ __device__ __forceinline__ void cfl_commit(const Args& a, int m, double qmax, bo
   const double v = block_max(bad ? -1.0 : qmax, s_red);
   // any thread's bad flag: encoded as a negative maximum is not enough (max
   // ignores it), so flag separately
-  if (bad) atomicOr(&a.ctl[m].flags, 1);
+  if (bad) atomicOr(&a.ctl[m].flags[slot], 1);
   if (threadIdx.x == 0 && v > 0.0)
     atomicMax(&a.ctl[m].qbits[slot], (unsigned long long)__double_as_longlong(v));
 }
@@ -304,10 +314,10 @@ static __global__ void k_ctl_init(Ctl* ctl, const double* t0, int nmeshes, int r
       c.qbits[s] = 0ull;
       c.t[s] = 0.0;
       c.steps[s] = 0;
+      c.flags[s] = 0;
     }
     c.t[ring] = t0 ? t0[m] : (keep ? t_old : 0.0);
     c.steps[ring] = (!t0 && keep) ? st_old : 0;
-    c.flags = 0;
   }
   if (m < 48 && queue) queue[m] = 0u;
 }

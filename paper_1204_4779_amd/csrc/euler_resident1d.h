@@ -98,7 +98,8 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   const double t_end = explicit_dt ? 0.0 : a.prm->t_end;
   const long long max_steps = explicit_dt ? 1 : a.prm->max_steps;
   const double cfl = explicit_dt ? 0.0 : a.prm->cfl;
-  bool bad = false;
+  // a non-physical input (flagged by the CFL reduction before the launch) is not stepped
+  bool bad = !explicit_dt && c.flags[a.ring] != 0;
   for (;;) {
     double dt;
     if (explicit_dt) {
@@ -153,10 +154,11 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     const int nx = (a.ring + 1) % 3, nn = (a.ring + 2) % 3;
     c.t[nx] = t;
     c.steps[nx] = steps;
+    c.flags[nx] = bad ? 1 : 0;
+    c.flags[nn] = 0;
     if (!explicit_dt) {
       c.qbits[nx] = (unsigned long long)__double_as_longlong(qmax);
       c.qbits[nn] = 0ull;
-      if (bad) c.flags |= 1;
     }
   }
 }

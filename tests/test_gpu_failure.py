@@ -1,0 +1,78 @@
+"""A state that turns non-physical part-way through paraiso_advance: the advance
+stops after the step that produced it, as the oracle's advance does, and
+reports NONFINITE with that step's time and count; the state buffers hold
+that step's output.  Input: a cold, randomly stirred patch (seed 30,
+amplitude 0.4, p = 1e-3) whose pressure goes negative in step 3 in FP64 and
+FP32 alike (the oracle's minimum pressure is 4.4e-5 after step 2 and -1.5e-3
+after step 3, margins far above either precision's rounding)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_4779_amd import binding as pb
+from paper_1204_4779_amd import inputs
+
+from gpu_util import TOL, as_input, field_errs, gpu_solver, gpu_state, oracle_mesh, spec_of
+
+pytestmark = pytest.mark.gpu
+
+FAMILIES = {
+    "march_fused": dict(tile=(64, 8), lds=2, fuse=1, threads=128),
+    "march": dict(tile=(64, 8), lds=2, fuse=0, threads=128),
+    "lds_fused": dict(tile=(16, 8), lds=1, fuse=1),
+    "lds": dict(tile=(16, 8), lds=1, fuse=0),
+    "direct": dict(tile=(16, 8), lds=0, fuse=0),
+}
+
+
+def failing_problem():
+    return inputs.cold_stirred_2d((40, 24), seed=30, amp=0.4)
+
+
+@pytest.mark.parametrize("t_end", [math.inf, 1.0])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("family", sorted(FAMILIES))
+def test_advance_stops_at_the_failing_step(family, dtype, t_end):
+    pr = failing_problem()
+    U = as_input(pr.U, dtype)
+    ref, t_ref, k_ref, ok = oracle.advance(oracle_mesh(pr), U, 0.5, t_end, max_steps=20, on_failure="return")
+    assert not ok and k_ref == 3
+    s = gpu_solver([spec_of(pr)], dtype, FAMILIES[family], pr.U)
+    print(f"failure advance: {family} {dtype} t_end={t_end}", flush=True)
+    with pytest.raises(pb.NonFiniteError) as ei:
+        s.advance(t_end, 0.5, max_steps=20)
+    assert ei.value.steps == [k_ref]
+    assert abs(ei.value.t[0] - t_ref) <= (1e-13 if dtype == "f64" else 1e-6) * t_ref
+    got = gpu_state(s)
+    errs = field_errs(got, ref)
+    tol = 1e-11 if dtype == "f64" else 2e-5
+    assert max(errs) <= tol, errs
+    # a second advance from the failed state takes no step and fails again
+    with pytest.raises(pb.NonFiniteError) as ei2:
+        s.advance(t_end, 0.5, max_steps=20, t0=ei.value.t)
+    assert ei2.value.steps == [0]
+    assert np.array_equal(gpu_state(s), got)
+    s.close()
+
+
+def test_batch_failing_mesh_stops_others_continue():
+    """Two meshes in one persistent launch per step: the failing mesh stops at its
+    step 3, the other one takes all 12 steps (FP64)."""
+    bad = failing_problem()
+    good = inputs.random_state(2, (40, 24), seed=77, bc=(0, 0))
+    specs = [spec_of(bad), spec_of(good)]
+    s = gpu_solver(specs, "f64", dict(FAMILIES["march_fused"], persistent=1), [bad.U, good.U])
+    with pytest.raises(pb.NonFiniteError) as ei:
+        s.advance(math.inf, 0.5, max_steps=12)
+    assert ei.value.steps == [3, 12]
+    ref_bad, t_bad, k_bad, ok = oracle.advance(oracle_mesh(bad), bad.U, 0.5, math.inf, max_steps=12,
+                                               on_failure="return")
+    ref_good, t_good, k_good = oracle.advance(oracle_mesh(good), good.U, 0.5, math.inf, max_steps=12)
+    assert (k_bad, k_good, ok) == (3, 12, False)
+    assert abs(ei.value.t[0] - t_bad) <= 1e-13 * t_bad
+    assert abs(ei.value.t[1] - t_good) <= 1e-13 * t_good
+    assert max(field_errs(gpu_state(s, 0), ref_bad)) <= 1e-11
+    assert max(field_errs(gpu_state(s, 1), ref_good)) <= 1e-11
+    s.close()
