@@ -21,6 +21,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "euler_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
 _COUNT_SRC = os.path.join(_HERE, "flopcount.cpp")
 _COUNT_PATH = os.path.join(_HERE, "liboracle_count.so")
 
@@ -49,6 +50,12 @@ def build(force: bool = True) -> str:
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
                                "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB_PATH)
+    if force or not os.path.exists(_OMP_PATH):
+        # the same source with its loops over cells run by OpenMP (bitwise the serial results)
+        tmp = _OMP_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _OMP_PATH)
     if force or not os.path.exists(_COUNT_PATH):
         tmp = _COUNT_PATH + ".tmp"
         subprocess.check_call(["g++", "-O1", "-std=c++17", "-fPIC", "-shared", "-fpermissive", "-w",
@@ -83,15 +90,29 @@ class Analytic:
         return a
 
 
-_lib = None
+_libs = {}
+_parallel = False
+
+
+def use_openmp(on: bool = True) -> None:
+    """Route the calls below to the OpenMP build (all host cores; results are
+    bitwise those of the serial build) or back to the serial one."""
+    global _parallel
+    _parallel = bool(on)
+
+
+def num_threads() -> int:
+    """Threads the current build's loops use (1 for the serial build)."""
+    return int(_load().orc_num_threads())
 
 
 def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+    key = "omp" if _parallel else "serial"
+    if key not in _libs:
+        path = _OMP_PATH if _parallel else _LIB_PATH
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         mp = ctypes.POINTER(_Mesh)
         lib.orc_stage.argtypes = [mp, dp, dp, ctypes.c_double, dp]
@@ -122,8 +143,10 @@ def _load():
                    "orc_advance", "orc_stage_t", "orc_step_t", "orc_advance_t", "orc_exact_prims", "orc_exact_state",
                    "orc_riemann_star"):
             getattr(lib, fn).restype = ctypes.c_int
-        _lib = lib
-    return _lib
+        lib.orc_num_threads.argtypes = []
+        lib.orc_num_threads.restype = ctypes.c_int
+        _libs[key] = lib
+    return _libs[key]
 
 
 @dataclass
@@ -236,14 +259,21 @@ def totals(mesh: Mesh, U) -> np.ndarray:
 
 
 def advance(mesh: Mesh, U0, cfl: float, t_end: float, max_steps: int = 1 << 40, t0: float = 0.0,
-            analytic: Analytic | None = None):
-    """Advance a copy of U0 to t_end; returns (U, t, steps)."""
+            analytic: Analytic | None = None, on_failure: str = "raise"):
+    """Advance a copy of U0 to t_end; returns (U, t, steps).  When the state
+    turns non-physical the advance stops after the step that produced it;
+    on_failure="raise" raises FloatingPointError, on_failure="return" returns
+    (U, t, steps, False) holding that step's output, time and count (and
+    (U, t, steps, True) on success)."""
     lib = _load()
     U = _as_state(mesh, U0).copy()
     t = ctypes.c_double(t0)
     steps = ctypes.c_int64()
-    _check(lib.orc_advance_t(ctypes.byref(mesh._c), _an(analytic), _ptr(U), float(cfl), float(t_end),
-                             int(max_steps), ctypes.byref(t), ctypes.byref(steps)), "advance")
+    rc = lib.orc_advance_t(ctypes.byref(mesh._c), _an(analytic), _ptr(U), float(cfl), float(t_end),
+                           int(max_steps), ctypes.byref(t), ctypes.byref(steps))
+    if on_failure == "return" and rc in (OK, NONFINITE):
+        return U, t.value, steps.value, rc == OK
+    _check(rc, "advance")
     return U, t.value, steps.value
 
 

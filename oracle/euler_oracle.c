@@ -51,6 +51,33 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* Built with -fopenmp, the per-cell and per-face loops below run on all host
+ * cores.  Every iteration writes its own cells or faces, the stage sums are
+ * formed per cell in the same order as serially, and the CFL maximum does not
+ * depend on the order of the fold: results are bitwise those of the serial
+ * build (the totals stay serial: their compensated sum is order-dependent). */
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_PARALLEL_CELLS _Pragma("omp parallel for collapse(3) schedule(static)")
+#define ORC_PARALLEL_FLAT _Pragma("omp parallel for schedule(static)")
+#define ORC_PARALLEL_MAX _Pragma("omp parallel for schedule(static) reduction(max: qmax) reduction(|: bad)")
+#define ORC_ATOMIC_WRITE _Pragma("omp atomic write")
+#else
+#define ORC_PARALLEL_CELLS
+#define ORC_PARALLEL_FLAT
+#define ORC_PARALLEL_MAX
+#define ORC_ATOMIC_WRITE
+#endif
+
+/* Threads the loops above use (1 in the serial build). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 #define ORC_OK 0
 #define ORC_BAD_ARG (-1)
 #define ORC_NONFINITE (-4)
@@ -436,6 +463,8 @@ static int pad_prims(const orc_mesh* m, const orc_analytic* an, double t, const 
   P->v = (double*)malloc(sizeof(double) * (size_t)nf * (size_t)P->np);
   if (!P->v) return ORC_NOMEM;
   const int64_t off[3] = {d > 0 ? NGHOST : 0, d > 1 ? NGHOST : 0, d > 2 ? NGHOST : 0};
+  int err = ORC_OK;
+  ORC_PARALLEL_CELLS
   for (int64_t k = 0; k < P->p[2]; ++k)
     for (int64_t j = 0; j < P->p[1]; ++j)
       for (int64_t i = 0; i < P->p[0]; ++i) {
@@ -452,8 +481,9 @@ static int pad_prims(const orc_mesh* m, const orc_analytic* an, double t, const 
           for (int a = 0; a < d; ++a) x[a] = ((double)g[a] + 0.5) * m->dx[a];
           int rc = orc_exact_prims(m, an, x, t, v);
           if (rc) {
-            free(P->v);
-            return rc;
+            ORC_ATOMIC_WRITE
+            err = rc;
+            continue;
           }
           for (int q = 0; q < nf; ++q) P->v[q * P->np + dst] = v[q];
           continue;
@@ -468,6 +498,10 @@ static int pad_prims(const orc_mesh* m, const orc_analytic* an, double t, const 
         orc_prim_of_cons(d, m->gamma, u, v);
         for (int q = 0; q < nf; ++q) P->v[q * P->np + dst] = v[q];
       }
+  if (err) {
+    free(P->v);
+    return err;
+  }
   return ORC_OK;
 }
 
@@ -507,6 +541,7 @@ int orc_stage_t(const orc_mesh* m, const orc_analytic* an, double t, const doubl
     }
     int64_t stride = 1;
     for (int b = 0; b < ax; ++b) stride *= P.p[b];
+    ORC_PARALLEL_CELLS
     for (int64_t k = 0; k < fe[2]; ++k)
       for (int64_t j = 0; j < fe[1]; ++j)
         for (int64_t i = 0; i < fe[0]; ++i) {
@@ -537,6 +572,7 @@ int orc_stage_t(const orc_mesh* m, const orc_analytic* an, double t, const doubl
     const double coef = cdt / m->dx[ax];
     int64_t fstride = 1;
     for (int b = 0; b < ax; ++b) fstride *= fe[b];
+    ORC_PARALLEL_CELLS
     for (int64_t k = 0; k < m->n[2]; ++k)
       for (int64_t j = 0; j < m->n[1]; ++j)
         for (int64_t i = 0; i < m->n[0]; ++i) {
@@ -548,6 +584,7 @@ int orc_stage_t(const orc_mesh* m, const orc_analytic* an, double t, const doubl
         }
     free(F);
   }
+  ORC_PARALLEL_FLAT
   for (int64_t e = 0; e < (int64_t)nf * N; ++e) Uout[e] = Ubase[e] + acc[e];
   free(acc);
   free(P.v);
@@ -589,23 +626,30 @@ int orc_cfl_qmax(const orc_mesh* m, const double* U, double* qmax_out) {
   if (rc) return rc;
   const int d = m->ndim, nf = d + 2;
   const int64_t N = ncells(m);
+  /* Every cell is checked; a bad cell anywhere makes the result NONFINITE.
+   * The maximum of the positive terms does not depend on the fold order. */
   double qmax = 0.0;
+  int bad = 0;
+  ORC_PARALLEL_MAX
   for (int64_t c = 0; c < N; ++c) {
     double u[5], v[5];
     for (int q = 0; q < nf; ++q) u[q] = U[q * N + c];
     orc_prim_of_cons(d, m->gamma, u, v);
     double rho = v[0], p = v[d + 1];
     if (!(rho > 0.0) || !(p > 0.0) || !isfinite(rho) || !isfinite(p) ||
-        !isfinite(u[d + 1]))
-      return ORC_NONFINITE;
+        !isfinite(u[d + 1])) {
+      bad = 1;
+      continue;
+    }
     double cs = sqrt(m->gamma * p / rho);
     double q = 0.0;
     for (int a = 0; a < d; ++a) {
-      if (!isfinite(v[1 + a])) return ORC_NONFINITE;
+      if (!isfinite(v[1 + a])) bad = 1;
       q += (fabs(v[1 + a]) + cs) / m->dx[a];
     }
-    qmax = (c == 0) ? q : fmax(qmax, q);
+    qmax = fmax(qmax, q);
   }
+  if (bad) return ORC_NONFINITE;
   *qmax_out = qmax;
   return ORC_OK;
 }

@@ -225,3 +225,84 @@ def uniform_flow(ndim: int, n: tuple, gamma: float = 1.4, rho: float = 1.3,
     v = [np.full(shape, vel[a]) for a in range(ndim)]
     return Problem("uniform", ndim, n3, gamma, tuple(bc) + (0,) * (3 - len(bc)),
                    conserved(gamma, r, v, np.full(shape, p)))
+
+
+def cold_stirred_2d(n: tuple, seed: int, amp: float, p0: float = 1e-3, gamma: float = 1.4,
+                    bc=(0, 0, 0)) -> Problem:
+    """A cold, randomly stirred patch: rho = exp(0.3 g0), v_a = amp g_{a+1} exp(-r^2 / 0.01)
+    with r the distance to the mesh centre (0.5, 0.5), p = p0 everywhere.  With a small p0
+    the stirring's kinetic energy dwarfs the internal energy, so for some seeds and
+    amplitudes the scheme reaches a non-physical state (p <= 0) after a few steps: the
+    input of the failure-handling tests."""
+    nx, ny = n[0], n[1]
+    count = nx * ny
+    shape = (ny, nx)
+    x = centres(nx)[None, :]
+    y = centres(ny)[:, None]
+    w = np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2) / 0.01)
+    rho = np.exp(0.3 * gaussian(seed, 0, count).reshape(shape))
+    vel = [amp * gaussian(seed, 1 + a, count).reshape(shape) * w for a in range(2)]
+    p = np.full(shape, float(p0))
+    return Problem("cold_stirred", 2, (nx, ny, 1), gamma, tuple(bc) + (0,) * (3 - len(bc)),
+                   conserved(gamma, rho, vel, p))
+
+
+# ----------------------------------------------------------------------------------------
+# the same generator in torch (any device): the large 3D boxes are generated where they
+# are used instead of on the host.  The uniforms are bit-identical to the numpy ones; the
+# Box-Muller transcendental functions of the device may differ from the host's libm in
+# the last bit of an FP64 value.
+# ----------------------------------------------------------------------------------------
+
+def _srl_t(z, k: int):
+    """Logical right shift of uint64 bit patterns held in an int64 tensor."""
+    return (z >> k) & ((1 << (64 - k)) - 1)
+
+
+def _signed(v: int) -> int:
+    v &= 0xFFFFFFFFFFFFFFFF
+    return v - (1 << 64) if v >= (1 << 63) else v
+
+
+def _mix_t(z):
+    z = (z ^ _srl_t(z, 30)) * _signed(int(_M1))
+    z = (z ^ _srl_t(z, 27)) * _signed(int(_M2))
+    return z ^ _srl_t(z, 31)
+
+
+def uniform_torch(seed: int, stream: int, count: int, start: int = 0, device="cpu"):
+    """`uniform` as a float64 torch tensor on `device` (same values, bit for bit)."""
+    import torch
+    k = torch.arange(start + 1, start + count + 1, dtype=torch.int64, device=device)
+    z = _mix_t(k * _signed(int(GOLDEN)) + _signed(int(_key(seed, stream))))
+    return _srl_t(z, 11).to(torch.float64) * (2.0 ** -53)
+
+
+def gaussian_torch(seed: int, stream: int, count: int, start: int = 0, device="cpu"):
+    import torch
+    u1 = 1.0 - uniform_torch(seed, 2 * stream, count, start, device)
+    u2 = uniform_torch(seed, 2 * stream + 1, count, start, device)
+    return torch.sqrt(-2.0 * torch.log(u1)) * torch.cos(2.0 * math.pi * u2)
+
+
+def turbulent_box_3d_torch(n: int = 256, seed: int = 4779, gamma: float = 5.0 / 3.0,
+                           z_range: tuple | None = None, device="cpu"):
+    """`turbulent_box_3d(...).U` for the planes z_range, as a float64 torch tensor of shape
+    (5, nz, n, n) on `device`."""
+    import torch
+    z0, z1 = (0, n) if z_range is None else z_range
+    nz = z1 - z0
+    count = nz * n * n
+    start = z0 * n * n
+    shape = (nz, n, n)
+    c0 = math.sqrt(gamma)
+    rho = torch.exp(0.5 * gaussian_torch(seed, 0, count, start, device)).reshape(shape)
+    out = torch.empty((5,) + shape, dtype=torch.float64, device=device)
+    out[0] = rho
+    kin = torch.zeros(shape, dtype=torch.float64, device=device)
+    for a in range(3):
+        v = 0.3 * c0 * gaussian_torch(seed, 1 + a, count, start, device).reshape(shape)
+        out[1 + a] = rho * v
+        kin += v * v
+    out[4] = 1.0 / (gamma - 1.0) + 0.5 * rho * kin
+    return out

@@ -594,3 +594,45 @@ def test_first_order_sod_against_exact():
         U, t, _ = oracle.advance(m, pr.U, 0.5, 0.2)
         errs[order] = float(np.mean(np.abs(U[0] - rho_ex)))
     assert errs[2] < errs[1] < 1e-2, errs
+
+
+# ---- the OpenMP build of the oracle (all host cores) ---------------------------------
+
+@pytest.mark.parametrize("ndim,n,bc", [(1, (257,), (1,)), (2, (37, 29), (0, 1)), (3, (11, 9, 7), (0, 0, 1))])
+def test_openmp_build_is_bitwise_serial(ndim, n, bc):
+    """Stage, step, CFL and advance of the OpenMP build equal the serial build's bit for bit
+    (rough states, both boundary kinds), and the failure of a non-physical state is the same."""
+    pr = inputs.random_state(ndim, n, seed=901 + ndim, rough=True, bc=bc)
+    m = oracle.Mesh(ndim, pr.n, pr.gamma, pr.bc)
+    res = {}
+    for par in (False, True):
+        oracle.use_openmp(par)
+        try:
+            dt = oracle.cfl_dt(m, pr.U, 0.5)
+            U1 = oracle.step(m, pr.U, dt)
+            Ua, ta, ka = oracle.advance(m, pr.U, 0.5, 1.0, max_steps=3)
+            bad = pr.U.copy()
+            bad[0].flat[len(bad[0].flat) // 2] = -1.0
+            with pytest.raises(FloatingPointError):
+                oracle.cfl_dt(m, bad, 0.5)
+            res[par] = (dt, U1, Ua, ta, ka, oracle.num_threads())
+        finally:
+            oracle.use_openmp(False)
+    s, p = res[False], res[True]
+    assert s[0] == p[0] and s[3] == p[3] and s[4] == p[4]
+    assert np.array_equal(s[1], p[1]) and np.array_equal(s[2], p[2])
+    assert s[5] == 1 and p[5] >= 1
+
+
+def test_openmp_build_analytic_ghosts_bitwise():
+    m = oracle.Mesh(2, (24, 20), 1.4, (oracle.ANALYTIC, oracle.ANALYTIC))
+    an = oracle.Analytic(oracle.SHOCK_TUBE, math.pi / 3)
+    U0 = oracle.exact_state(m, an, 0.05)
+    out = []
+    for par in (False, True):
+        oracle.use_openmp(par)
+        try:
+            out.append(oracle.advance(m, U0, 0.5, 0.07, t0=0.05, analytic=an))
+        finally:
+            oracle.use_openmp(False)
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1:] == out[1][1:]
