@@ -4,10 +4,14 @@ shock tube; coaxial and rotated by 60 degrees) with the exact solution in
 the ghost cells, against the FP64 oracle.
 
 One step from the oracle's exact state at t0 > 0 with an explicit dt: FP64
-within 1e-12 and FP32 within 1e-5, each field against its natural scale
-(momentum against rho (|v| + c), since the sound wave's and the tube's
-momenta start at or near zero).  Meshes span several tiles and end in a
-ragged tile, so interior tiles, edge tiles and corners all read ghosts.
+within 1e-12 and FP32 within 1e-5.  Density and energy are held pointwise
+(every cell against its own value) and normwise.  In FP64 the momenta are
+held against their own maximum too, except the sound wave's: its momentum is
+of the order of the amplitude (1e-5) while its flux carries the O(1)
+pressure, so the rounding of that pressure term, not the scheme, sets its
+own-scale error; it is held, as every FP32 momentum is, against
+max rho (|v| + c).  Meshes span several tiles and end in a ragged tile, so
+interior tiles, edge tiles and corners all read ghosts.
 """
 import math
 
@@ -17,7 +21,7 @@ import pytest
 import oracle
 from paper_1204_4779_amd import binding as pb
 
-from gpu_util import TOL, as_input, gpu_state, state_err
+from gpu_util import TOL, as_input, gpu_state, measures, rel_err, state_err
 
 pytestmark = pytest.mark.gpu
 
@@ -26,6 +30,13 @@ KINDS = {"entropy": pb.ENTROPY_WAVE, "sound": pb.SOUND_WAVE, "sod": pb.SHOCK_TUB
 OBLIQUE = math.pi / 3
 # the one-stage register march, ghost cells from the ghost arrays
 MARCH = dict(tile=(64, 8), lds=2, fuse=0, threads=256)
+
+
+def _err(got, ref, kind, dtype):
+    """The bar's measure for this problem and precision (see the module docstring)."""
+    if dtype == "f64" and kind != "sound":
+        return rel_err(got, ref)
+    return state_err(got, ref, 1.4)
 
 
 def _problem(kind, angle):
@@ -66,8 +77,8 @@ def test_one_step_2d_matches_oracle(dtype, kind, angle):
     an = _problem(kind, angle)
     for variant in (None, dict(tile=(16, 8), lds=1, fuse=0, persistent=1), MARCH, dict(MARCH, tile=(64, 4))):
         got, ref, _, _ = _one_step(2, (37, 29), (A, A), dtype, an, 0.07, variant)
-        err = state_err(got, ref, 1.4)
-        print(f"  {kind} angle {angle:.3f} {dtype} {variant}: {err:.3e}", flush=True)
+        err = _err(got, ref, kind, dtype)
+        print(f"  {kind} angle {angle:.3f} {dtype} {variant}: {err:.3e} {measures(got, ref, 1.4)}", flush=True)
         assert err <= TOL[dtype], (variant, err)
 
 
@@ -76,10 +87,12 @@ def test_one_step_2d_matches_oracle(dtype, kind, angle):
 def test_one_step_1d_and_3d_match_oracle(dtype, kind):
     got, ref, _, _ = _one_step(1, (203,), (A,), dtype, _problem(kind, 0.0), 0.05,
                                dict(tile=(64, 1, 1), lds=1, fuse=0))
-    assert state_err(got, ref, 1.4) <= TOL[dtype]
+    print(f"  1D {kind} {dtype}: {measures(got, ref, 1.4)}", flush=True)
+    assert _err(got, ref, kind, dtype) <= TOL[dtype]
     # 3D: the problem lives in the x-y plane; z periodic (the solution is z-independent)
     got, ref, _, _ = _one_step(3, (19, 11, 6), (A, A, pb.PERIODIC), dtype, _problem(kind, OBLIQUE), 0.05)
-    assert state_err(got, ref, 1.4) <= TOL[dtype]
+    print(f"  3D {kind} {dtype}: {measures(got, ref, 1.4)}", flush=True)
+    assert _err(got, ref, kind, dtype) <= TOL[dtype]
 
 
 def test_analytic_axis_mixes_with_periodic_and_outflow():
@@ -88,7 +101,7 @@ def test_analytic_axis_mixes_with_periodic_and_outflow():
         an = _problem("entropy", 0.0 if bc[0] == A else math.pi / 2)
         for variant in (None, MARCH):
             got, ref, _, _ = _one_step(2, (33, 18), bc, "f64", an, 0.11, variant)
-            assert state_err(got, ref, 1.4) <= 1e-12, (bc, variant)
+            assert rel_err(got, ref) <= 1e-12, (bc, variant)
 
 
 def test_explicit_steps_carry_the_time():
@@ -97,7 +110,7 @@ def test_explicit_steps_carry_the_time():
     for variant in (None, MARCH):
         got, ref, tg, t = _one_step(2, (40, 24), (A, A), "f64", _problem("sod", OBLIQUE), 0.02, variant, nsteps=3)
         assert tg == t
-        assert state_err(got, ref, 1.4) <= 1e-12
+        assert rel_err(got, ref) <= 1e-12
 
 
 def test_time_survives_cfl_and_variant_changes():
@@ -145,7 +158,8 @@ def test_advance_matches_oracle():
             got = gpu_state(s)
             s.close()
             assert t == [t_end] and n == [n_ref], (kind, variant)
-            assert state_err(got, ref, 1.4) < 1e-11, (kind, variant)
+            print(f"  advance {kind} {variant}: {measures(got, ref, 1.4)}", flush=True)
+            assert _err(got, ref, kind, "f64") < 1e-11, (kind, variant)
 
 
 def _l1_gpu(kind, angle, n, t_end, dtype="f64", variant=None):

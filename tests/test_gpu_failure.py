@@ -1,10 +1,14 @@
 """A state that turns non-physical part-way through paraiso_advance: the advance
 stops after the step that produced it, as the oracle's advance does, and
 reports NONFINITE with that step's time and count; the state buffers hold
-that step's output.  Input: a cold, randomly stirred patch (seed 30,
-amplitude 0.4, p = 1e-3) whose pressure goes negative in step 3 in FP64 and
-FP32 alike (the oracle's minimum pressure is 4.4e-5 after step 2 and -1.5e-3
-after step 3, margins far above either precision's rounding)."""
+that step's output.  Input: a cold, randomly stirred patch (seed 23,
+amplitude 0.5, p = 1e-3) whose pressure goes negative in the output of step
+3 in FP64 and FP32 alike, while every state that step's fluxes are computed
+from stays physical: the oracle's minimum pressure is 2.3e-4 after step 2,
+9.3e-5 in step 3's stage-1 state and -5.4e-5 after step 3, margins far above
+either precision's rounding.  (A stage-1 state that is already non-physical
+would make the failing step's output depend on how each side evaluates a
+sound speed from a negative pressure, which no definition fixes.)"""
 import math
 
 import numpy as np
@@ -28,7 +32,24 @@ FAMILIES = {
 
 
 def failing_problem():
-    return inputs.cold_stirred_2d((40, 24), seed=30, amp=0.4)
+    return inputs.cold_stirred_2d((40, 24), seed=23, amp=0.5)
+
+
+def _pmin(U):
+    m2 = U[1] ** 2 + U[2] ** 2
+    return float(np.min(0.4 * (U[3] - 0.5 * m2 / U[0])))
+
+
+def assert_stage1_physical(pr, U):
+    """The failing step's inputs and its stage-1 state are physical by a wide margin; only
+    its output is not (so the output is fixed by the scheme on both sides)."""
+    m = oracle_mesh(pr)
+    U2, _, k, ok = oracle.advance(m, U, 0.5, math.inf, max_steps=2, on_failure="return")
+    assert ok and k == 2
+    dt = oracle.cfl_dt(m, U2, 0.5)
+    U1 = oracle.stage(m, U2, U2, 0.5 * dt)
+    assert _pmin(U2) > 1e-4 and _pmin(U1) > 5e-5
+    assert _pmin(oracle.stage(m, U1, U2, dt)) < -5e-5
 
 
 @pytest.mark.parametrize("t_end", [math.inf, 1.0])
@@ -39,6 +60,7 @@ def test_advance_stops_at_the_failing_step(family, dtype, t_end):
     U = as_input(pr.U, dtype)
     ref, t_ref, k_ref, ok = oracle.advance(oracle_mesh(pr), U, 0.5, t_end, max_steps=20, on_failure="return")
     assert not ok and k_ref == 3
+    assert_stage1_physical(pr, U)
     s = gpu_solver([spec_of(pr)], dtype, FAMILIES[family], pr.U)
     print(f"failure advance: {family} {dtype} t_end={t_end}", flush=True)
     with pytest.raises(pb.NonFiniteError) as ei:
