@@ -118,6 +118,26 @@ def state_err(got: np.ndarray, ref: np.ndarray, gamma: float) -> float:
     return max(state_scaled_err(got, ref, gamma), pointwise_err(got, ref))
 
 
+def strict_err(got: np.ndarray, ref: np.ndarray, gamma: float, zero: float = 1e-10) -> float:
+    """The strict measure for fields that may vanish in exact arithmetic: every
+    field normwise against its own maximum, except a momentum component whose
+    own maximum is below `zero` times max rho (|v| + c) (a component that is
+    zero in exact arithmetic and holds only rounding, such as the transverse
+    momentum of a wave along an axis), which has no scale of its own and is
+    measured against max rho (|v| + c); density and energy also pointwise."""
+    d = ref.shape[0] - 2
+    rho = ref[0]
+    m2 = sum(ref[1 + a] ** 2 for a in range(d))
+    c = np.sqrt(gamma * np.maximum((gamma - 1.0) * (ref[d + 1] - 0.5 * m2 / rho), 0.0) / rho)
+    mscale = float(np.max(np.sqrt(m2) + rho * c))
+    worst = pointwise_err(got, ref)
+    for q in range(ref.shape[0]):
+        own = float(np.max(np.abs(ref[q])))
+        scale = mscale if (1 <= q <= d and own < zero * mscale) else own
+        worst = max(worst, float(np.max(np.abs(got[q] - ref[q]))) / scale)
+    return worst
+
+
 def measures(got: np.ndarray, ref: np.ndarray, gamma: float) -> dict:
     """Every measure, for the logs: strict per field, pointwise rho and E, state-scaled."""
     return {"per_field": [float(f"{e:.3e}") for e in field_errs(got, ref)],
