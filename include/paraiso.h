@@ -198,6 +198,29 @@ int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, parai
 int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the CFL
+ * time step of paraiso_cfl_dt without a context or workspace.
+ * dt_out[m] = cfl / max_i sum_a (|v_a| + c)/dx_a over the state in buffer
+ * `buffer` (0 or 1) of meshes[m], in FP64, for 1 <= count <=
+ * PARAISO_STATIC_MESHES meshes that share ndim and dtype; it reads ndim,
+ * dtype, n, dx, gamma and state[buffer] of each descriptor (bc and order do
+ * not enter the CFL term).  Results equal paraiso_cfl_dt's bit for bit (same
+ * reduction kernel).  The mesh table and the reduction's control blocks live
+ * in a fixed device array of the library (at most 32 KiB per device, held
+ * until the process ends); nothing is allocated on the host or the device.
+ * Every call on a device shares that device's array, so calls that overlap
+ * on one device (other threads, other streams) race.  Synchronous on
+ * `hip_stream`, which must belong to the current device.
+ * Errors: INVALID_ARG (null pointers, count < 1, buffer not 0/1, cfl outside
+ * (0, 1], an invalid descriptor), UNSUPPORTED (count > PARAISO_STATIC_MESHES,
+ * more than 2^31 - 1 cells, device index > 63), NONFINITE, HIP.
+ */
+#define PARAISO_STATIC_MESHES 64
+int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t count, int32_t buffer, double cfl,
+                              double* dt_out, void* hip_stream);
+
+/*
  * One midpoint-RK2 step of every mesh with the caller's time steps
  * dt[m] >= 0 (finite): F0 = Flux(U0), U1 = AddFlux(dt/2, F0, U0),
  * F1 = Flux(U1), U2 = AddFlux(dt, F1, U0) (section "Tuning Experiments / The

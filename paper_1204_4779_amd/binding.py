@@ -21,6 +21,7 @@ ERR_UNSUPPORTED = -2
 ERR_HIP = -3
 ERR_NONFINITE = -4
 ERR_WORKSPACE = -5
+STATIC_MESHES = 64   # PARAISO_STATIC_MESHES: capacity of paraiso_cfl_dt_static
 
 PERIODIC = 0
 OUTFLOW = 1
@@ -37,7 +38,7 @@ EXPORTS = ("paraiso_workspace_bytes", "paraiso_init", "paraiso_set_variant", "pa
            "paraiso_version", "paraiso_set_analytic", "paraiso_exact_state", "paraiso_set_time", "paraiso_get_time",
            "paraiso_wave_workspace_bytes", "paraiso_wave_prepare", "paraiso_wave_run",
            "paraiso_wave_advance", "paraiso_mlp_sizes", "paraiso_mlp_forward", "paraiso_mlp_loss_grad",
-           "paraiso_mlp_adam")
+           "paraiso_mlp_adam", "paraiso_cfl_dt_static")
 
 
 class ParaisoError(RuntimeError):
@@ -119,6 +120,7 @@ def load(path: str | None = None):
         "paraiso_get_variant": ([vp, varp], i32),
         "paraiso_default_variant": ([mp, i32, varp], i32),
         "paraiso_cfl_dt": ([vp, dbl, dp], i32),
+        "paraiso_cfl_dt_static": ([ctypes.POINTER(paraiso_mesh), i32, i32, dbl, dp, vp], i32),
         "paraiso_step": ([vp, dp], i32),
         "paraiso_advance": ([vp, dbl, dbl, i64, dp, ctypes.POINTER(i64)], i32),
         "paraiso_current": ([vp, ctypes.POINTER(i32)], i32),
@@ -198,6 +200,15 @@ def paraiso_get_variant(ctx: int) -> paraiso_variant:
 def paraiso_cfl_dt(ctx: int, cfl: float, count: int = 1) -> list:
     out = (ctypes.c_double * count)()
     _check(load().paraiso_cfl_dt(ctypes.c_void_p(ctx), float(cfl), out))
+    return list(out)
+
+
+def paraiso_cfl_dt_static(meshes, buffer: int, cfl: float, stream: int) -> list:
+    """dt per mesh from the state in `buffer` of each descriptor, without a context
+    (the library's fixed device scratch; see include/paraiso.h)."""
+    arr = (paraiso_mesh * len(meshes))(*meshes)
+    out = (ctypes.c_double * len(meshes))()
+    _check(load().paraiso_cfl_dt_static(arr, len(meshes), int(buffer), float(cfl), out, ctypes.c_void_p(stream)))
     return list(out)
 
 

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -22,15 +23,18 @@
 using namespace paraiso;
 
 namespace {
-thread_local std::string g_err;
+// message of the last failure on this thread, in a fixed buffer so that
+// setting it never allocates (the no-allocation entry point reports through it)
+thread_local char g_err[512];
 }
 
-void paraiso_set_error(const std::string& msg) { g_err = msg; }
+void paraiso_set_error_text(const char* msg) { std::snprintf(g_err, sizeof(g_err), "%s", msg); }
+void paraiso_set_error(const std::string& msg) { paraiso_set_error_text(msg.c_str()); }
 
 namespace {
 
 int fail(int code, const std::string& msg) {
-  g_err = msg;
+  paraiso_set_error(msg);
   return code;
 }
 
@@ -711,7 +715,7 @@ int check_problems(const paraiso_ctx* c) {
 
 extern "C" {
 
-const char* paraiso_last_error(void) { return g_err.c_str(); }
+const char* paraiso_last_error(void) { return g_err; }
 
 const char* paraiso_version(void) { return "paraiso-mi355x 0.1 (gfx950)"; }
 
@@ -831,9 +835,9 @@ int32_t paraiso_set_variant(paraiso_ctx* c, const paraiso_variant* v) {
   paraiso_variant old = c->var;
   int rc = apply_variant(c, *v);
   if (rc) {
-    std::string msg = g_err;
+    const std::string msg = g_err;
     apply_variant(c, old);
-    g_err = msg;
+    paraiso_set_error(msg);
   }
   return rc;
 }

@@ -208,3 +208,19 @@ def test_wave_entry_points_validate_before_any_device_work(lib):
         with pytest.raises(pb.ParaisoError) as ei:
             pb.paraiso_wave_run(*args, 0)
         assert ei.value.code == pb.ERR_INVALID_ARG, args
+
+
+def test_static_cfl_host_validation(lib):
+    """paraiso_cfl_dt_static rejects its arguments before touching the device."""
+    m = _mesh()
+    for meshes, buf, cfl, code in (([m] * (pb.STATIC_MESHES + 1), 0, 0.5, pb.ERR_UNSUPPORTED),
+                                   ([m], 2, 0.5, pb.ERR_INVALID_ARG), ([m], 0, 0.0, pb.ERR_INVALID_ARG),
+                                   ([m], 0, 1.5, pb.ERR_INVALID_ARG), ([m, _mesh(dtype=pb.F64)], 0, 0.5, pb.ERR_INVALID_ARG),
+                                   ([_mesh(ndim=4)], 0, 0.5, pb.ERR_INVALID_ARG), ([_mesh(gamma=0.5)], 0, 0.5, pb.ERR_INVALID_ARG)):
+        with pytest.raises(pb.ParaisoError) as ei:
+            pb.paraiso_cfl_dt_static(meshes, buf, cfl, 0)
+        assert ei.value.code == code
+        assert "cfl_dt_static" in lib.paraiso_last_error().decode()
+    with pytest.raises(pb.ParaisoError) as ei:
+        pb.paraiso_cfl_dt_static([], 0, 0.5, 0)
+    assert ei.value.code == pb.ERR_INVALID_ARG
