@@ -59,9 +59,9 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes, each scaled by the reading of a plain 512 MiB device copy
 # (factors 2.000 and 1.000); valid only for the kernel sources they were taken
 # on (hash of the device headers) and the variant named.
-TRAFFIC = {"sources": "2b7b39f7cf1e073e",
+TRAFFIC = {"sources": "b95a9084b64bc2fa",
            "variant": {"tile": [64, 20], "lds": 2, "fuse": 1, "waves_per_eu": 0, "threads": 256},
-           "bytes_per_launch": 157.7e6}
+           "bytes_per_launch": 157.76e6}
 
 
 def kernel_name(v: dict) -> str:
@@ -288,6 +288,10 @@ def box_entries(n: int, steps: int, warmup: int, untuned: bool = True) -> dict:
         uv = dict(variants.UNTUNED_3D)
         r = run_gpu(None, "f32", uv, max(steps // 4, 6), min(warmup, 12), specs=[spec], fill=box_fill(n))
         out["f32_untuned"] = config_entry(r, n ** 3, 3, "f32", uv)
+    # the other member of the fusion pair: one-stage march if the tuned one is fused, else the fused march
+    other = dict(variants.ONE_STAGE_3D) if var.get("fuse") else dict(variants.FUSED_3D)
+    r = run_gpu(None, "f32", other, steps, warmup, specs=[spec], fill=box_fill(n))
+    out["f32_fused_march" if other["fuse"] else "f32_one_stage_march"] = config_entry(r, n ** 3, 3, "f32", other)
     return out
 
 

@@ -322,3 +322,306 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
 }
 
 }  // namespace paraiso
+
+namespace paraiso {
+
+// ---------------------------------------------------------------------------
+// Fused 3D register march: both Runge-Kutta stages in one launch, the
+// stage-1 state held on chip (the midpoint state of the time-marching
+// equations "delayed" rather than stored).
+//
+// A block of NW waves owns a 56-column strip (64 lanes, 4 halo columns per
+// side) and NW stage-1 rows; wave w computes stage 1 on row yb - 2 + w and,
+// for 2 <= w < NW - 2, stage 2 on row yb + w - 2, so a block outputs NW - 4
+// rows.  Marching along z, push k brings input plane first + k:
+//   phase A: the primitives of the wave's own row (waves 0..3 also one of
+//            the 4 halo rows) go to the LDS plane V0 (double-buffered), and
+//            the stage-1 primitives of plane k - 3, finished in the previous
+//            push, to the LDS plane V1 (double-buffered); one barrier;
+//   phase B: stage 2 forms the y-faces of V1 plane k - 3 (3-slot ring G2),
+//            pushes that plane into its z-pipeline and assembles plane k - 5
+//            (base U0, x-faces by lane shifts, y-faces from the ring);
+//            stage 1 forms the y-faces of V0 plane k (3-slot ring G1),
+//            pushes it into its z-pipeline and assembles plane k - 2, whose
+//            primitives wait in registers for the next push's phase A.
+// Every face flux of each stage is evaluated once per block; the 4 extra
+// stage-1 rows per block are the price of keeping U1 on chip.  Periodic
+// meshes only (the stage-1 state of a ghost cell is that of the cell it
+// wraps to).
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct FusedPlaneMarch {
+  Fields<T, 3> U0, Uout;
+  Gas<T> g;
+  T kx1, ky1, kz1, kx2, ky2, kz2;
+  double inv_dx[3];
+  double gamma;
+  int nz, plane, first, Z;        // Z: output planes of the chunk
+  unsigned own_bytes, halo_bytes;
+  int wave, NW, lane, hrel;
+  bool has_halo, out_wave, store_lane, cfl;
+  T* sV0;  // [2][5][NW + 4][64]
+  T* sV1;  // [2][5][NW][64]
+  T* sG1;  // [3][5][NW + 1][64]
+  T* sG2;  // [3][5][NW - 3][64]
+  RowPipe5<T> P1, P2;
+  T u_nx[5], uh_nx[5], b1_nx[5], b2_nx[5];  // next push's own row, halo row, stage-1 and stage-2 bases
+  T v1p[5];                                 // stage-1 primitives of the plane finished last push
+  double qmax;
+  bool bad;
+
+  __device__ __forceinline__ unsigned hide(unsigned b) const {
+    asm volatile("" : "+v"(b));
+    return b;
+  }
+  static __device__ __forceinline__ __attribute__((address_space(1))) T* at(
+      __attribute__((address_space(1))) T* row, unsigned bytes) {
+    return (__attribute__((address_space(1))) T*)((__attribute__((address_space(1))) char*)row + bytes);
+  }
+  __device__ __forceinline__ int zoff(int k) const { return map_index(first + k, nz, kPeriodic) * plane; }
+
+  // loads of push k: own row and halo row of plane k, the bases of the
+  // planes assembled in push k (stage 1: k - 2, stage 2: k - 5)
+  __device__ __forceinline__ void load(int k) {
+    const unsigned ob = hide(own_bytes);
+    const int zo = zoff(k);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) u_nx[q] = *at(U0.f[q] + zo, ob);
+    if (has_halo && k <= Z + 5) {
+      const unsigned hb = hide(halo_bytes);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) uh_nx[q] = *at(U0.f[q] + zo, hb);
+    }
+    if (k >= 4) {
+      const int z1 = zoff(k - 2);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) b1_nx[q] = *at(U0.f[q] + z1, ob);
+    }
+    if (out_wave && k >= 9) {
+      const int z2 = zoff(k - 5);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) b2_nx[q] = *at(U0.f[q] + z2, ob);
+    }
+  }
+
+  __device__ __forceinline__ void push(int k) {
+    T u[5], uh[5], b1[5], b2[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      u[q] = u_nx[q];
+      uh[q] = uh_nx[q];
+      b1[q] = b1_nx[q];
+      b2[q] = b2_nx[q];
+    }
+    if (k + 1 < Z + 9) load(k + 1);
+    const int NR = NW + 4;
+    // phase A
+    T v0[5];
+    prim_of_cons<T, 3>(u, v0, g);
+    {
+      T* V = sV0 + (k & 1) * (5 * NR * 64);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) V[(q * NR + wave + 2) * 64 + lane] = v0[q];
+      if (has_halo && k <= Z + 5) {
+        T vh[5];
+        prim_of_cons<T, 3>(uh, vh, g);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) V[(q * NR + hrel) * 64 + lane] = vh[q];
+      }
+    }
+    const bool s2in = k >= 5;  // V1 plane k - 3 exists (stage-1 planes 2 .. Z + 5)
+    if (s2in) {
+      T* V = sV1 + ((k - 3) & 1) * (5 * NW * 64);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) V[(q * NW + wave) * 64 + lane] = v1p[q];
+    }
+    __syncthreads();
+    // phase B, stage 2: y-faces of V1 plane k - 3, then assemble plane k - 5
+    if (s2in && out_wave) {
+      if (k >= 7 && k <= Z + 6) {  // the y-faces of stage-2 planes 4 .. Z + 3
+        const T* V = sV1 + ((k - 3) & 1) * (5 * NW * 64);
+        T* Gs = sG2 + ((k - 3) % 3) * (5 * (NW - 3) * 64);
+        T vl[5], vr[5], G[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T* c = V + (q * NW + wave - 2) * 64 + lane;
+          face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+        }
+        hllc<T, 3, 1>(vl, vr, G, g);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Gs[(q * (NW - 3) + wave - 2) * 64 + lane] = G[q];
+        if (wave == NW - 3) {
+#pragma unroll
+          for (int q = 0; q < 5; ++q) {
+            const T* c = V + (q * NW + wave - 1) * 64 + lane;
+            face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+          }
+          hllc<T, 3, 1>(vl, vr, G, g);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) Gs[(q * (NW - 3) + wave - 1) * 64 + lane] = G[q];
+        }
+      }
+      T dz[5], va[5];
+      if (pipe_push5<T>(P2, v1p, k - 5, g, dz, va)) {  // k >= 9: plane k - 5
+        T dF[5];
+        xflux_diff3<T>(va, g, dF);
+        const T* Gs = sG2 + ((k - 5) % 3) * (5 * (NW - 3) * 64);
+        T out[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T dy = Gs[(q * (NW - 3) + wave - 2) * 64 + lane] - Gs[(q * (NW - 3) + wave - 1) * 64 + lane];
+          out[q] = fma(kz2, dz[q], fma(ky2, dy, fma(kx2, dF[q], b2[q])));
+        }
+        if (store_lane) {
+          const int zo = zoff(k - 5);
+          const unsigned ob = hide(own_bytes);
+#pragma unroll
+          for (int q = 0; q < 5; ++q) *at(Uout.f[q] + zo, ob) = out[q];
+          if (cfl) {
+            const double qv = cfl_q<T, 3>(out, inv_dx, gamma);
+            bad |= !(qv > 0.0);
+            qmax = qv > qmax ? qv : qmax;
+          }
+        }
+      }
+    }
+    // phase B, stage 1: y-faces of V0 plane k, then assemble plane k - 2
+    if (k >= 2 && k <= Z + 5) {
+      const T* V = sV0 + (k & 1) * (5 * NR * 64);
+      T* Gs = sG1 + (k % 3) * (5 * (NW + 1) * 64);
+      T vl[5], vr[5], G[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T* c = V + (q * NR + wave) * 64 + lane;
+        face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+      }
+      hllc<T, 3, 1>(vl, vr, G, g);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + wave) * 64 + lane] = G[q];
+      if (wave == NW - 1) {
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const T* c = V + (q * NR + wave + 1) * 64 + lane;
+          face_states(c[0], c[64], c[128], c[192], vl[q], vr[q]);
+        }
+        hllc<T, 3, 1>(vl, vr, G, g);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) Gs[(q * (NW + 1) + NW) * 64 + lane] = G[q];
+      }
+    }
+    T dz[5], va[5];
+    if (k <= Z + 7 && pipe_push5<T>(P1, v0, k < 4 ? k : 4, g, dz, va)) {  // k >= 4: plane k - 2
+      T dF[5];
+      xflux_diff3<T>(va, g, dF);
+      const T* Gs = sG1 + ((k - 2) % 3) * (5 * (NW + 1) * 64);
+      T u1[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const T dy = Gs[(q * (NW + 1) + wave) * 64 + lane] - Gs[(q * (NW + 1) + wave + 1) * 64 + lane];
+        u1[q] = fma(kz1, dz[q], fma(ky1, dy, fma(kx1, dF[q], b1[q])));
+      }
+      prim_of_cons<T, 3>(u1, v1p, g);
+    }
+  }
+
+  __device__ __forceinline__ void run() {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) uh_nx[q] = b1_nx[q] = b2_nx[q] = v1p[q] = T(0);
+    load(0);
+#pragma clang loop unroll(disable)
+    for (int k = 0; k < Z + 9; ++k) push(k);
+  }
+};
+
+template <typename T, int W>
+__global__ void __launch_bounds__(sizeof(T) == 8 ? 384 : 768) PARAISO_WAVES_ATTR(W) k_march3d_fused(Args a, LdsGeom) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[16];
+  __shared__ int s_item;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int NW = blockDim.x >> 6;
+  T* sV0 = reinterpret_cast<T*>(smem);
+  T* sV1 = sV0 + 2 * 5 * (NW + 4) * 64;
+  T* sG1 = sV1 + 2 * 5 * NW * 64;
+  T* sG2 = sG1 + 3 * 5 * (NW + 1) * 64;
+  ItemLoop it{0, 1};
+  for (int item; (item = next_item(a, it, &s_item, 0)) >= 0;) {
+    item = __builtin_amdgcn_readfirstlane(item);
+    const Tile t = tile_of(a, item);
+    const MeshDev& M = a.meshes[t.m];
+    bool active;
+    const double dt = step_dt(a, t.m, active);
+    if (t.first && threadIdx.x == 0) step_bookkeeping(a, t.m, dt, active);
+    const int nx = M.n[0], ny = M.n[1], nz = M.n[2];
+    const int x0 = t.org[0], yb = t.org[1], z0 = t.org[2];
+    const int z1 = min(z0 + a.tile[2], nz);
+    const int col = map_index(x0 - 4 + lane, nx, kPeriodic);
+    const bool out_wave = wave >= 2 && wave < NW - 2;
+    const int yout = yb + wave - 2;                                // stage-2 row (out_wave)
+    const int yown = map_index(yb - 2 + wave, ny, kPeriodic);     // stage-1 row
+    // halo rows of V0: waves 0,1 take stage-1 rows -2, -1; waves 2,3 take NW, NW + 1
+    const bool has_halo = wave < 4;
+    const int hrel = wave < 2 ? wave : NW + wave;                  // LDS row of the halo row
+    const int yhalo = map_index(yb - 4 + hrel, ny, kPeriodic);
+    const bool store_lane = out_wave && lane >= 4 && lane < 60 && (x0 - 4 + lane) < nx && yout < ny;
+    const Fields<T, 3> U0 = fields<T, 3>(M.s[a.src]);
+    const Fields<T, 3> Uout = fields<T, 3>(M.s[1 - a.src]);
+    const int plane = nx * ny;
+    double qmax = 0.0;
+    bool bad = false;
+    if (!active) {
+      if (out_wave && yout < ny) {
+        const int gr = yout * nx + col;
+        for (int z = z0; z < z1; ++z) {
+          const int gi = z * plane + gr;
+#pragma unroll
+          for (int q = 0; q < 5; ++q)
+            if (store_lane) Uout.f[q][gi] = U0.f[q][gi];
+        }
+      }
+    } else {
+      FusedPlaneMarch<T> S;
+      S.U0 = uniform(U0);
+      S.Uout = uniform(Uout);
+      S.g = gas_of<T>(M);
+      S.kx1 = (T)(0.5 * dt * M.inv_dx[0]);
+      S.ky1 = (T)(0.5 * dt * M.inv_dx[1]);
+      S.kz1 = (T)(0.5 * dt * M.inv_dx[2]);
+      S.kx2 = (T)(dt * M.inv_dx[0]);
+      S.ky2 = (T)(dt * M.inv_dx[1]);
+      S.kz2 = (T)(dt * M.inv_dx[2]);
+#pragma unroll
+      for (int x = 0; x < 3; ++x) S.inv_dx[x] = M.inv_dx[x];
+      S.gamma = M.gamma;
+      S.nz = nz;
+      S.plane = plane;
+      S.first = z0 - 4;
+      S.Z = z1 - z0;
+      S.own_bytes = (unsigned)(yown * nx + col) * (unsigned)sizeof(T);
+      S.halo_bytes = (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T);
+      S.wave = wave;
+      S.NW = NW;
+      S.lane = lane;
+      S.hrel = hrel;
+      S.has_halo = has_halo;
+      S.out_wave = out_wave;
+      S.store_lane = store_lane;
+      S.cfl = a.cfl != 0;
+      S.sV0 = sV0;
+      S.sV1 = sV1;
+      S.sG1 = sG1;
+      S.sG2 = sG2;
+      S.qmax = 0.0;
+      S.bad = false;
+      S.run();
+      qmax = S.qmax;
+      bad = S.bad;
+      __syncthreads();  // LDS reuse by the next item
+    }
+    if (a.cfl && active) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);
+  }
+}
+
+}  // namespace paraiso

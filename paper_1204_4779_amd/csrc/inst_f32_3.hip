@@ -34,6 +34,8 @@ const KernelTable* table_f32_3() {
       (const void*)k_exact_state<float, 3>,
       nullptr,
       (int)sizeof(float),
+      {(const void*)k_march3d_fused<float, 0>, (const void*)k_march3d_fused<float, 3>,
+       (const void*)k_march3d_fused<float, 4>, (const void*)k_march3d_fused<float, 5>},
   };
   return &t;
 }

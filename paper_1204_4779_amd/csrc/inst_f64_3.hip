@@ -34,6 +34,8 @@ const KernelTable* table_f64_3() {
       (const void*)k_exact_state<double, 3>,
       nullptr,
       (int)sizeof(double),
+      {(const void*)k_march3d_fused<double, 0>, (const void*)k_march3d_fused<double, 3>,
+       (const void*)k_march3d_fused<double, 4>, (const void*)k_march3d_fused<double, 5>},
   };
   return &t;
 }

@@ -26,6 +26,7 @@ struct KernelTable {
   const void* exact_state;       // exact solution of an analytic problem into a state buffer
   const void* analytic_ghosts;   // the ghost arrays of 2D analytic meshes for one step (2D)
   int elem_bytes;
+  const void* march3d_fused[4];  // 3D register march, both stages in one launch (null for other dimensions)
 };
 
 const KernelTable* table_f32_1();

@@ -250,6 +250,11 @@ struct paraiso_ctx {
   int device = 0, num_cus = 0, max_lds = 0;
   bool ctl_ready = false;          // the control ring holds a time to keep
   std::vector<char> analytic_set;  // per mesh: problem given by paraiso_set_analytic
+  // pinned host staging for the synchronous calls' small copies (the
+  // parameter block and start times of an advance, the control blocks read
+  // back): page-locked, so each copy is one DMA instead of a staged one
+  char* h_pin = nullptr;
+  size_t pin_ctl = 0;  // offset of the control-block area
 };
 
 namespace {
@@ -393,6 +398,13 @@ bool march_offsets_fit(const paraiso_mesh* meshes, int count) {
   return true;
 }
 
+// Dynamic LDS of the fused 3D march with nw waves: V0 and V1 planes
+// (double-buffered, nw + 4 and nw rows), stage-1 and stage-2 y-flux rings
+// (3 slots, nw + 1 and nw - 3 faces), 5 fields of 64 lanes each.
+size_t march3d_fused_lds(int nw, int esize) {
+  return (size_t)esize * 5 * 64 * (2 * (size_t)(nw + 4) + 2 * (size_t)nw + 3 * (size_t)(nw + 1) + 3 * (size_t)(nw - 3));
+}
+
 int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string& why) {
   const int d = c->ndim;
   for (int a = 0; a < 3; ++a) {
@@ -428,8 +440,19 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
             return why = "fused register march needs periodic boundaries", PARAISO_ERR_UNSUPPORTED;
       if (v.threads != 0 && (v.threads < 64 || v.threads > 256 || v.threads % 64))
         return why = "register march: threads must be 64, 128, 192 or 256", PARAISO_ERR_UNSUPPORTED;
+    } else if (v.fuse) {
+      for (const auto& m : c->meshes)
+        if (m.bc[0] != PARAISO_PERIODIC || m.bc[1] != PARAISO_PERIODIC || m.bc[2] != PARAISO_PERIODIC)
+          return why = "fused 3D register march needs periodic boundaries", PARAISO_ERR_UNSUPPORTED;
+      if (v.tile[1] < 6 || v.tile[1] > 12)
+        return why = "fused 3D register march: tile[1] (stage-1 rows = waves per block) must be 6..12",
+               PARAISO_ERR_UNSUPPORTED;
+      if (v.threads != 0 && v.threads != 64 * v.tile[1])
+        return why = "fused 3D register march: threads must be 64 * tile[1]", PARAISO_ERR_UNSUPPORTED;
+      if (march3d_fused_lds(v.tile[1], c->esize) + 16 * sizeof(double) + 64 > (size_t)c->max_lds)
+        return why = "fused 3D register march: LDS of " + std::to_string(v.tile[1]) + " rows exceeds the limit",
+               PARAISO_ERR_UNSUPPORTED;
     } else {
-      if (v.fuse) return why = "3D register march is a one-stage kernel (fuse = 0)", PARAISO_ERR_UNSUPPORTED;
       if (v.tile[1] != 4 && v.tile[1] != 8)
         return why = "3D register march: tile[1] (rows = waves per block) must be 4 or 8", PARAISO_ERR_UNSUPPORTED;
       if (v.threads != 0 && v.threads != 64 * v.tile[1])
@@ -472,7 +495,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
     et[0] = 64 - 2 * (v.fuse ? 4 : 2);
     et[1] = v.fuse ? march2d_item_rows(threads / 64, v.tile[1]) : v.tile[1] * (threads / 64);
   } else if (v.lds == 2) {
-    et[0] = 60;  // rows = waves, planes = tile[2]
+    et[0] = v.fuse ? 56 : 60;              // 64 lanes less 4 (fused) or 2 halo columns per side
+    et[1] = v.fuse ? v.tile[1] - 4 : v.tile[1];  // output rows: waves, less 4 stage-1 halo rows when fused
   }
   // items
   int64_t items = 0;
@@ -530,7 +554,8 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   }
   if (v.lds == 2 && d == 3) {
     const int nw = v.tile[1];
-    shmem = (size_t)c->esize * 5 * 64 * (2 * (size_t)(nw + 4) + 3 * (size_t)(nw + 1));
+    shmem = v.fuse ? march3d_fused_lds(nw, c->esize)
+                   : (size_t)c->esize * 5 * 64 * (2 * (size_t)(nw + 4) + 3 * (size_t)(nw + 1));
     if (shmem + 16 * sizeof(double) + 64 > (size_t)c->max_lds)
       return fail(PARAISO_ERR_UNSUPPORTED, "variant: 3D march needs " + std::to_string(shmem) + " bytes of LDS");
   }
@@ -550,7 +575,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   const int ws = waves_slot(v.waves_per_eu);
   Launch L;
   if (v.lds == 3) L.fn = c->tab->resident1d;
-  else if (v.lds == 2 && d == 3) L.fn = c->tab->march3d_stage[ws];
+  else if (v.lds == 2 && d == 3) L.fn = v.fuse ? c->tab->march3d_fused[ws] : c->tab->march3d_stage[ws];
   else if (v.lds == 2)
     L.fn = v.fuse ? c->tab->march_fused[ws]
                   : (any_analytic(c->meshes.data(), c->count) ? c->tab->march_stage_an[ws] : c->tab->march_stage[ws]);
@@ -702,6 +727,9 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
   if (count > 1) v->persistent = 1;
 }
 
+// The control-block area of the pinned staging buffer.
+Ctl* pinned_ctl(paraiso_ctx* c) { return reinterpret_cast<Ctl*>(c->h_pin + c->pin_ctl); }
+
 // Every analytic mesh needs its exact solution before it can be stepped.
 int check_problems(const paraiso_ctx* c) {
   for (int m = 0; m < c->count; ++m)
@@ -768,6 +796,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   c->tab = table_for(c->dtype, c->ndim);
   auto bail = [&](int code) {
     if (c->cap) hipStreamDestroy(c->cap);
+    if (c->h_pin) hipHostFree(c->h_pin);
     delete c;
     return code;
   };
@@ -775,6 +804,8 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&c->max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+  c->pin_ctl = align256((L.dt - L.params) + sizeof(double) * count);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_pin, c->pin_ctl + sizeof(Ctl) * count, hipHostMallocDefault);
   if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("device query: ") + hipGetErrorString(e)));
   // host mesh table
   c->hm.resize(count);
@@ -860,8 +891,8 @@ int32_t paraiso_cfl_dt(paraiso_ctx* c, double cfl, double* dt_out) {
   int rc = ctl_init(c, nullptr);
   if (!rc) rc = launch_cfl(c);
   if (rc) return rc;
-  std::vector<Ctl> h(c->count);
-  HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+  const Ctl* h = pinned_ctl(c);
+  HIP_TRY(hipMemcpyAsync((void*)h, c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int m = 0; m < c->count; ++m) {
     if (h[m].flags[c->ring]) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": non-physical state");
@@ -896,20 +927,24 @@ int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_st
   if (std::isnan(t_end) || t_end == -INFINITY) return fail(PARAISO_ERR_INVALID_ARG, "t_end must be a number or +inf");
   for (int m = 0; m < c->count; ++m)
     if (!std::isfinite(t_inout[m])) return fail(PARAISO_ERR_INVALID_ARG, "t_inout must be finite");
-  Params p{t_end, cfl, (long long)max_steps};
-  HIP_TRY(hipMemcpyAsync(c->d_params, &p, sizeof(p), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(c->d_dt, t_inout, sizeof(double) * c->count, hipMemcpyHostToDevice, c->stream));
+  // the parameter block and the start times, adjacent in the workspace, in one copy
+  const Params p{t_end, cfl, (long long)max_steps};
+  const size_t dt_off = c->L.dt - c->L.params;
+  std::memcpy(c->h_pin, &p, sizeof(p));
+  std::memcpy(c->h_pin + dt_off, t_inout, sizeof(double) * c->count);
+  HIP_TRY(hipMemcpyAsync(c->d_params, c->h_pin, dt_off + sizeof(double) * c->count, hipMemcpyHostToDevice,
+                         c->stream));
   int rc = ctl_init(c, c->d_dt);
   if (!rc) rc = launch_cfl(c);
   if (rc) return rc;
-  std::vector<Ctl> h(c->count);
+  Ctl* h = pinned_ctl(c);
   if (c->resident) {
     // the whole advance in one launch; it counts as one buffer flip
     rc = enqueue_step(c, c->cur, c->ring, false, c->stream);
     if (rc) return rc;
     c->cur ^= 1;
     c->ring = (c->ring + 1) % 3;
-    HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     for (int m = 0; m < c->count; ++m) {
       t_inout[m] = h[m].t[c->ring];
@@ -926,7 +961,7 @@ int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_st
     rc = run_steps(c, chunk);
     if (rc) return rc;
     launched += chunk;
-    HIP_TRY(hipMemcpyAsync(h.data(), c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(h, c->d_ctl, sizeof(Ctl) * c->count, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     bool done = true;
     int64_t want = 0;
@@ -1044,6 +1079,7 @@ int32_t paraiso_destroy(paraiso_ctx* c) {
   if (!c) return PARAISO_OK;
   drop_graphs(c);
   if (c->cap) hipStreamDestroy(c->cap);
+  if (c->h_pin) hipHostFree(c->h_pin);
   delete c;
   return PARAISO_OK;
 }

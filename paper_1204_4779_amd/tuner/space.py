@@ -2,9 +2,9 @@
 
 A variant is (tile per axis, staging, RK-stage fusion, waves-per-EU hint).
 Staging: 0 = each cell reads its stencil from global memory, 1 = LDS tiles,
-2 = register march (2D only: a wave per 64-column strip marching along y,
-x-neighbours through DPP lane shifts; tile[0] is then 64 and tile[1] the
-rows per wave).  The genome is its bit string: 2 bits per active axis for
+2 = register march (a wave per 64-column strip, x-neighbours through DPP lane
+shifts; tile[0] is then 64; 2D: tile[1] rows per wave marching along y; 3D:
+tile[1] rows = waves per block marching along z, fused or one stage).  The genome is its bit string: 2 bits per active axis for
 the tile (8, 16, 32, 64), 2 bits for staging, 1 bit for fusion, 2 bits for
 the hint (0 = compiler's choice, 3, 4, 5).  The paper's genome encodes Manifest /
 Delayed choices and launch configurations of generated code ("Tuning
@@ -24,7 +24,8 @@ import itertools
 import math
 
 TILE_VALUES = (8, 16, 32, 64)
-MARCH3D_ROWS = (4, 8, 16, 32)   # rows (= waves) per block of the 3D register march; 16, 32 invalid
+MARCH3D_ROWS = (4, 8, 12, 16)   # rows (= waves) per block of the 3D register march: 4, 8 one stage;
+                                # 8, 12 fused (stage-1 rows; 16 exceeds the LDS)
 WAVE_VALUES = (0, 3, 4, 5)
 KMAXR = 8                  # cells per thread the LDS kernels keep in registers
 MAX_LDS_BYTES = 160 * 1024  # per workgroup on gfx950
@@ -74,12 +75,22 @@ def lds_bytes(variant: dict, ndim: int, esize: int) -> int:
     return esize * (ndim + 2) * (vin + fmax + kept)
 
 
+def march3d_fused_lds(rows: int, esize: int) -> int:
+    """Dynamic LDS of the fused 3D march: two primitive planes of rows + 4 and rows
+    rows, two 3-slot y-flux rings of rows + 1 and rows - 3 faces, 5 fields x 64 lanes."""
+    return esize * 5 * 64 * (2 * (rows + 4) + 2 * rows + 3 * (rows + 1) + 3 * (rows - 3))
+
+
 def statically_valid(variant: dict, ndim: int, esize: int) -> bool:
     if variant["lds"] == 2:
         if ndim == 2:
             return variant["tile"][0] == 64
-        return (ndim == 3 and variant["tile"][0] == 64 and variant["tile"][1] in (4, 8)
-                and not variant["fuse"])
+        if ndim != 3 or variant["tile"][0] != 64:
+            return False
+        rows = variant["tile"][1]
+        if not variant["fuse"]:
+            return rows in (4, 8)
+        return 6 <= rows <= 12 and march3d_fused_lds(rows, esize) + STATIC_LDS <= MAX_LDS_BYTES
     if not variant["lds"]:
         return True
     if lds_bytes(variant, ndim, esize) + STATIC_LDS > MAX_LDS_BYTES:

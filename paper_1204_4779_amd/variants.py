@@ -39,5 +39,12 @@ TUNED = {
 }
 
 
+# the fused 3D register march (both stages in one launch, U1 on chip):
+# 12 stage-1 rows per block of 12 waves (8 output rows), 64-plane chunks
+FUSED_3D = dict(tile=(64, 12, 64), lds=2, fuse=1, waves_per_eu=0)
+# the one-stage 3D register march (two launches per step, U1 in the workspace)
+ONE_STAGE_3D = dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3)
+
+
 def tuned(workload: str, dtype: str) -> dict:
     return dict(TUNED[(workload, dtype)])

@@ -52,7 +52,7 @@ def test_kh2048_full_field(dtype):
 
 
 def test_box256_full_field():
-    # every cell of the 3D box at 256^3, tuned register march and the fused LDS tile
+    # every cell of the 3D box at 256^3: tuned register march, fused LDS tile, fused register march
     print("case box256 f32 full field", flush=True)
     pr = inputs.turbulent_box_3d(256, seed=4779)
     U0 = as_input(pr.U, "f32")
@@ -64,7 +64,8 @@ def test_box256_full_field():
     finally:
         oracle.use_openmp(False)
     del U0
-    for v in (variants.tuned("box256", "f32"), dict(tile=(8, 8, 8), lds=1, fuse=1, threads=256)):
+    for v in (variants.tuned("box256", "f32"), dict(tile=(8, 8, 8), lds=1, fuse=1, threads=256),
+              dict(tile=(64, 12, 64), lds=2, fuse=1)):
         s = gpu_solver(spec_of(pr), "f32", v, pr.U)
         got_dt = s.cfl_dt(0.5)[0]
         assert abs(got_dt - dt) <= 1e-14 * dt

@@ -282,9 +282,20 @@ def test_register_march_rejects_unsupported():
     pr3 = inputs.random_state(3, (8, 8, 8), seed=1)
     s3 = gpu_solver(spec_of(pr3), "f32", None, pr3.U)
     with pytest.raises(pb.ParaisoError):
-        s3.set_variant(dict(tile=(64, 8, 16), lds=2, fuse=1))  # 3D march is one stage
+        s3.set_variant(dict(tile=(64, 4, 16), lds=2, fuse=1))  # fused 3D march: 6..12 stage-1 rows
+    with pytest.raises(pb.ParaisoError):
+        s3.set_variant(dict(tile=(64, 14, 16), lds=2, fuse=1))
     with pytest.raises(pb.ParaisoError):
         s3.set_variant(dict(tile=(64, 2, 16), lds=2, fuse=0))  # 4 or 8 rows per block
+    s3.set_variant(dict(tile=(64, 12, 16), lds=2, fuse=1))
+    s3d = gpu_solver(spec_of(pr3), "f64", None, pr3.U)
+    with pytest.raises(pb.ParaisoError):
+        s3d.set_variant(dict(tile=(64, 8, 16), lds=2, fuse=1))  # FP64: the LDS holds 6 rows
+    s3d.set_variant(dict(tile=(64, 6, 16), lds=2, fuse=1))
+    pr3o = inputs.random_state(3, (8, 8, 8), seed=1, bc=(0, 1, 0))
+    s3o = gpu_solver(spec_of(pr3o), "f32", None, pr3o.U)
+    with pytest.raises(pb.ParaisoError):
+        s3o.set_variant(dict(tile=(64, 8, 16), lds=2, fuse=1))  # fused 3D march needs periodic
     pr1 = inputs.random_state(1, (100,), seed=1)
     s1 = gpu_solver(spec_of(pr1), "f32", None, pr1.U)
     with pytest.raises(pb.ParaisoError):
@@ -306,6 +317,44 @@ def test_register_march_3d_matches_oracle(dtype, bc, n):
         s.step(dt)
         err = rel_err(gpu_state(s), ref)
         assert err <= TOL[dtype], (v, err)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [(19, 11, 10), (70, 9, 7), (130, 20, 5), (5, 4, 3), (60, 26, 70), (120, 7, 2)])
+def test_register_march_3d_fused_matches_oracle(dtype, n):
+    # the fused 3D march: stage-1 rows 6..12 (FP64: 6, its LDS limit), plane
+    # chunks of 1, 3, 16 and 64 planes (chunk seams inside the mesh and a
+    # chunk longer than the mesh), meshes narrower and wider than a strip
+    pr = inputs.random_state(3, n, seed=500 + n[0] + n[2], rough=True)
+    U0 = as_input(pr.U, dtype)
+    m = oracle_mesh(pr)
+    dt = oracle.cfl_dt(m, U0, 0.5)
+    ref = oracle.step(m, U0, dt)
+    shapes = ((6, 16), (6, 1), (6, 64)) if dtype == "f64" else ((8, 16), (12, 3), (6, 64), (10, 1), (12, 64))
+    for rows, planes in shapes:
+        v = dict(tile=(64, rows, planes), lds=2, fuse=1)
+        print(f"case fused 3D march {dtype} {n} {v}", flush=True)
+        s = gpu_solver(spec_of(pr), dtype, v, pr.U)
+        got_dt = s.cfl_dt(0.5)[0]
+        assert abs(got_dt - dt) <= 1e-14 * dt
+        s.step(dt)
+        err = rel_err(gpu_state(s), ref)
+        assert err <= TOL[dtype], (v, err)
+        s.close()
+
+
+def test_register_march_3d_fused_advance_matches_oracle():
+    # device-resident dt through the six-step graphs, FP64 and FP32
+    pr = inputs.random_state(3, (40, 24, 20), seed=78)
+    ref, t_ref, n_ref = oracle.advance(oracle_mesh(pr), pr.U, 0.5, 1e9, max_steps=8)
+    for dtype, rows in (("f64", 6), ("f32", 12)):
+        s = gpu_solver(spec_of(pr), dtype, dict(tile=(64, rows, 16), lds=2, fuse=1), pr.U)
+        t, n = s.advance(1e9, 0.5, max_steps=8)
+        tol_t = 1e-13 if dtype == "f64" else 1e-6
+        assert n == [8] and abs(t[0] - t_ref) <= tol_t * t_ref
+        ref_in = oracle.advance(oracle_mesh(pr), as_input(pr.U, dtype), 0.5, 1e9, max_steps=8)[0]
+        assert rel_err(gpu_state(s), ref_in) < (1e-11 if dtype == "f64" else 1e-4)
+        s.close()
 
 
 def test_register_march_2d_unfused_outflow():

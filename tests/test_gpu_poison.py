@@ -27,6 +27,7 @@ CASES = [
     (2, (130, 90), (0, 0), dict(tile=(64, 8), lds=2, fuse=1, threads=256)),
     (2, (130, 90), (1, 1), dict(tile=(64, 8), lds=2, fuse=0, threads=256)),
     (3, (40, 20, 24), (0, 0, 0), dict(tile=(64, 4, 16), lds=2, fuse=0)),
+    (3, (70, 20, 24), (0, 0, 0), dict(tile=(64, 6, 16), lds=2, fuse=1)),
     (3, (19, 11, 10), (1, 0, 0), dict(tile=(8, 4, 4), lds=1, fuse=1)),
 ]
 
