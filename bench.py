@@ -429,8 +429,12 @@ def other_workload(name: str, steps: int, warmup: int, sizes=None, with_cpu: boo
         return dict(e, workload="sod_1d_1024_outflow_fp64_to_t0.2", unit="cell-updates/s", dtype="f64")
     if name in ("box256", "box512"):
         n = 256 if name == "box256" else 512
-        e = box_entries(n, steps, warmup, untuned=False)["f32_tuned"]
-        return dict(e, workload=f"box3d_{n}^3_periodic_fp32", unit="cell-updates/s", dtype="f32")
+        es = box_entries(n, steps, warmup, untuned=False)
+        out = dict(es["f32_tuned"], workload=f"box3d_{n}^3_periodic_fp32", unit="cell-updates/s", dtype="f32")
+        for k in ("f32_fused_march", "f32_one_stage_march"):
+            if k in es:
+                out[k] = es[k]
+        return out
     if name == "batch512":
         e = batch_entries(steps, warmup, untuned=False)
         return dict(e["f32_tuned"], workload="batch_512_uneven_2d_periodic_fp32", unit="cell-updates/s",

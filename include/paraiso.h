@@ -105,8 +105,11 @@ typedef struct paraiso_mesh {
  *                   periodic boundaries, and with at least 2 waves of at
  *                   least 6 rows its waves share stage-1 rows through LDS
  *                   (a block then covers waves * rows - 2 rows); 3D:
- *                   tile[1] = 4 or 8 rows (= waves) per block, tile[2]
- *                   planes per block, one stage per launch (fuse = 0);
+ *                   tile[2] planes per block; one stage per launch
+ *                   (fuse = 0): tile[1] = 4 or 8 rows (= waves) per
+ *                   block; fused (fuse = 1, periodic meshes): tile[1] =
+ *                   6..12 stage-1 rows (= waves) per block, of which
+ *                   tile[1] - 4 are output rows (FP64: 6, the LDS limit);
  *                3: resident (1D, at most 4096 cells per mesh in FP32 and
  *                   3407 in FP64, the LDS of one workgroup holding
  *                   8 * (6n + 3) bytes): one workgroup per mesh runs a
