@@ -121,7 +121,8 @@ typedef struct paraiso_mesh {
  *                minimum waves per SIMD the kernel is compiled for, which
  *                caps registers per lane at 168, 128 or 100;
  *   threads      workgroup size, a multiple of 64 in [64, 512], or 0 for
- *                the default of the chosen kernel;
+ *                the default of the chosen kernel (the 3D register march:
+ *                64 * tile[1], up to 768 when fused);
  *   manifest     what an LDS tile (lds = 1) keeps between the phases of an
  *                axis, the paper's Manifest/Delayed choice for the results
  *                of the interpolation and of the Riemann solver (section

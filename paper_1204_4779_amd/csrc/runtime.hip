@@ -473,7 +473,9 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   if (v.persistent != 0 && v.persistent != 1) return why = "persistent must be 0 or 1", PARAISO_ERR_UNSUPPORTED;
   if (!(v.waves_per_eu == 0 || v.waves_per_eu == 3 || v.waves_per_eu == 4 || v.waves_per_eu == 5))
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
-  if (v.threads != 0 && (v.threads < 64 || v.threads > 512 || v.threads % 64))
+  // (the fused 3D march runs one wave per stage-1 row, up to 768 threads; its own check below)
+  const bool fused3d = v.lds == 2 && c->ndim == 3 && v.fuse;
+  if (v.threads != 0 && !fused3d && (v.threads < 64 || v.threads > 512 || v.threads % 64))
     return why = "threads must be 0 or a multiple of 64 in [64, 512]", PARAISO_ERR_UNSUPPORTED;
   const int64_t tc = (int64_t)v.tile[0] * v.tile[1] * v.tile[2];
   if (tc > (1 << 22)) return why = "tile has more than 2^22 cells", PARAISO_ERR_UNSUPPORTED;

@@ -72,7 +72,11 @@ def gain_study(db: DB, ndim: int, esize: int, seeds: int = 15, frac: float = 0.1
             log(f"{name} seed {s}: best {tr.best_mu / truth.best_mu:.4f} of optimum, anytime "
                 f"{res[-1]['anytime']:.4f}, after {len(tr.evaluated)} benchmarks, {tr.spent:.1f} s")
         out["runs"][name] = res
-        out[f"{name}_median"] = float(np.median([r["best_frac"] for r in res]))
+        best = [r["best_frac"] for r in res]
+        out[f"{name}_median"] = float(np.median(best))
+        out[f"{name}_mean"] = float(np.mean(best))
+        out[f"{name}_min"] = float(np.min(best))
+        out[f"{name}_hits"] = int(sum(1 for b in best if b >= 1.0 - 1e-12))   # seeds that found the optimum
         out[f"{name}_anytime_median"] = float(np.median([r["anytime"] for r in res]))
     return out
 

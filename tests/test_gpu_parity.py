@@ -288,6 +288,9 @@ def test_register_march_rejects_unsupported():
     with pytest.raises(pb.ParaisoError):
         s3.set_variant(dict(tile=(64, 2, 16), lds=2, fuse=0))  # 4 or 8 rows per block
     s3.set_variant(dict(tile=(64, 12, 16), lds=2, fuse=1))
+    s3.set_variant(dict(tile=(64, 12, 16), lds=2, fuse=1, threads=768))  # the tuner names the threads
+    with pytest.raises(pb.ParaisoError):
+        s3.set_variant(dict(tile=(64, 12, 16), lds=2, fuse=1, threads=512))
     s3d = gpu_solver(spec_of(pr3), "f64", None, pr3.U)
     with pytest.raises(pb.ParaisoError):
         s3d.set_variant(dict(tile=(64, 8, 16), lds=2, fuse=1))  # FP64: the LDS holds 6 rows
