@@ -322,6 +322,31 @@ static __global__ void k_ctl_init(Ctl* ctl, const double* t0, int nmeshes, int r
   if (m < 48 && queue) queue[m] = 0u;
 }
 
+// Start of paraiso_advance for up to kInlineMeshes meshes, with the
+// parameter block and the start times passed by value (no host-to-device
+// copy): writes the parameter block, then resets each mesh's control ring at
+// slot `ring` as k_ctl_init does with a time array.
+constexpr int kInlineMeshes = 16;
+struct InlineTimes {
+  double t[kInlineMeshes];
+};
+static __global__ void k_advance_init(Ctl* ctl, Params* prm, Params p, InlineTimes t0, int nmeshes, int ring,
+                                      unsigned int* queue) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m == 0) *prm = p;
+  if (m < nmeshes) {
+    Ctl& c = ctl[m];
+    for (int s = 0; s < 3; ++s) {
+      c.qbits[s] = 0ull;
+      c.t[s] = 0.0;
+      c.steps[s] = 0;
+      c.flags[s] = 0;
+    }
+    c.t[ring] = t0.t[m];
+  }
+  if (m < 48 && queue) queue[m] = 0u;
+}
+
 constexpr int kChunk = 4096;  // cells per block in the standalone reductions
 
 __device__ __forceinline__ int find_mesh_chunk(const MeshDev* ms, int nm, int chunk) {
@@ -346,6 +371,9 @@ __global__ void __launch_bounds__(256) k_cfl(Args a) {
   const int c1 = min(c0 + kChunk, M.ncells);
   double qmax = 0.0;
   bool bad = false;
+  // four cells per thread in flight: the loads of the next iterations are
+  // issued before this one's arithmetic
+#pragma unroll 4
   for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
     T u[D + 2];
 #pragma unroll

@@ -929,14 +929,24 @@ int32_t paraiso_advance(paraiso_ctx* c, double t_end, double cfl, int64_t max_st
   if (std::isnan(t_end) || t_end == -INFINITY) return fail(PARAISO_ERR_INVALID_ARG, "t_end must be a number or +inf");
   for (int m = 0; m < c->count; ++m)
     if (!std::isfinite(t_inout[m])) return fail(PARAISO_ERR_INVALID_ARG, "t_inout must be finite");
-  // the parameter block and the start times, adjacent in the workspace, in one copy
   const Params p{t_end, cfl, (long long)max_steps};
-  const size_t dt_off = c->L.dt - c->L.params;
-  std::memcpy(c->h_pin, &p, sizeof(p));
-  std::memcpy(c->h_pin + dt_off, t_inout, sizeof(double) * c->count);
-  HIP_TRY(hipMemcpyAsync(c->d_params, c->h_pin, dt_off + sizeof(double) * c->count, hipMemcpyHostToDevice,
-                         c->stream));
-  int rc = ctl_init(c, c->d_dt);
+  int rc = PARAISO_OK;
+  if (c->count <= kInlineMeshes) {
+    // parameter block and start times as kernel arguments: no copy
+    InlineTimes t0{};
+    for (int m = 0; m < c->count; ++m) t0.t[m] = t_inout[m];
+    hipLaunchKernelGGL(k_advance_init, dim3(1), dim3(64), 0, c->stream, c->d_ctl, c->d_params, p, t0, c->count,
+                       c->ring, c->d_queue);
+    HIP_TRY(hipGetLastError());
+  } else {
+    // the parameter block and the start times, adjacent in the workspace, in one copy
+    const size_t dt_off = c->L.dt - c->L.params;
+    std::memcpy(c->h_pin, &p, sizeof(p));
+    std::memcpy(c->h_pin + dt_off, t_inout, sizeof(double) * c->count);
+    HIP_TRY(hipMemcpyAsync(c->d_params, c->h_pin, dt_off + sizeof(double) * c->count, hipMemcpyHostToDevice,
+                           c->stream));
+    rc = ctl_init(c, c->d_dt);
+  }
   if (!rc) rc = launch_cfl(c);
   if (rc) return rc;
   Ctl* h = pinned_ctl(c);
