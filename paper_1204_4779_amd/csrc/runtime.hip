@@ -674,7 +674,7 @@ void lds_variant(int ndim, paraiso_variant* v) {
 //   1D: the resident kernel when every mesh fits one workgroup's LDS
 //       (160 KiB on gfx950), else LDS tiles;
 //   2D: the fused register march when every mesh is periodic on both axes
-//       (FP32 20 rows x 4 waves, FP64 40 rows x 2 waves), else LDS tiles;
+//       (FP32 20 rows x 4 waves, FP64 40 rows x 4 waves), else LDS tiles;
 //   3D: the register march, 4 rows x 64-plane chunks, at most 168 VGPRs.
 // Batches pull tiles from the persistent queue.
 void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) {
@@ -715,7 +715,7 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
       v->tile[1] = f64 ? 40 : 20;
       v->lds = 2;
       v->fuse = 1;
-      v->threads = f64 ? 128 : 256;
+      v->threads = 256;
     }
   } else {
     v->tile[0] = 64;

@@ -15,9 +15,10 @@ TUNED = {
     # occupancy hint on top of the exhaustive search (whose tile axis has
     # 8/16/32/64 only).  FP32: <= 128 VGPRs, 4 waves per SIMD, and 37 strips x
     # 27 row blocks = 999 blocks of 4 waves, all resident at once; FP64: 2
-    # waves per SIMD.
+    # waves per SIMD, 37 strips x 13 row blocks of 158 rows = 481 blocks of 4
+    # waves (36.1-36.8 G against 35.3-35.7 G for 2 waves of 40 rows).
     ("kh2048", "f32"): dict(tile=(64, 20), lds=2, fuse=1, waves_per_eu=0, threads=256),
-    ("kh2048", "f64"): dict(tile=(64, 40), lds=2, fuse=1, waves_per_eu=0, threads=128),
+    ("kh2048", "f64"): dict(tile=(64, 40), lds=2, fuse=1, waves_per_eu=0, threads=256),
     # 3D register march, one stage per launch: 60 columns x 4 rows per block,
     # 64-plane chunks, VGPRs capped at 168 (3 waves per SIMD)
     ("box256", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3),

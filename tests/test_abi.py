@@ -109,7 +109,7 @@ def test_default_variant(lib):
     v = pb.paraiso_default_variant([_mesh()])
     assert (v.lds, v.fuse, tuple(v.tile)) == (2, 1, (64, 20, 1)) and v.threads == 256
     v = pb.paraiso_default_variant([_mesh(dtype=pb.F64)])
-    assert (v.lds, tuple(v.tile), v.threads) == (2, (64, 40, 1), 128)
+    assert (v.lds, tuple(v.tile), v.threads) == (2, (64, 40, 1), 256)
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, 1, 0))])
     assert v.lds == 1 and v.fuse == 1 and v.persistent == 1
     # 3D: the one-stage register march
