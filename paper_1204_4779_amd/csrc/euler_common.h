@@ -378,9 +378,7 @@ __global__ void __launch_bounds__(256) k_cfl(Args a) {
     T u[D + 2];
 #pragma unroll
     for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][c];
-    const double q = cfl_q<T, D>(u, M.inv_dx, M.gamma);
-    bad |= !(q > 0.0);
-    qmax = fmax(qmax, q);
+    cfl_fold(cfl_q<T, D>(u, M.inv_dx, M.gamma), qmax, bad);
   }
   cfl_commit(a, m, qmax, bad, s_red, a.ring);
 }

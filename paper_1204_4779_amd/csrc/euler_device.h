@@ -248,14 +248,17 @@ __device__ __forceinline__ void hllc(const T* vl, const T* vr, T* f, const Gas<T
   f[D + 1] = uk * (ek + pk) + w * (estar - ek);
 }
 
-// CFL quantity sum_a (|v_a| + c)/dx_a of one cell, in FP64; returns a
-// negative value for a non-physical or non-finite state.  Evaluated as
+// CFL quantity sum_a (|v_a| + c)/dx_a of one cell, in FP64.  Evaluated as
 // (sum_a (|m_a| + rho c)/dx_a) / rho with (rho c)^2 = gamma rho p and
 // rho p = (gamma - 1)(rho E - |m|^2/2), so the reciprocal of rho and the
-// reciprocal square root of gamma rho p are independent chains.  With
-// rho > 0, every other failure (p <= 0, a NaN or infinite component) makes
-// q NaN on its way through that reciprocal square root, so one test for
-// rho > 0 and one for q < inf cover them all.
+// reciprocal square root of gamma rho p are independent chains.  The result
+// is positive and finite exactly when the state is physical (rho > 0,
+// p > 0, every component finite): p <= 0, a NaN or an infinite component,
+// or rho = 0 make gamma rho p zero, negative, infinite or NaN, and q NaN on
+// its way through the reciprocal square root (0 * inf, inf * 0, or the root
+// of a negative number); rho < 0 with gamma rho p > 0 leaves q < 0; a
+// subnormal rho, whose reciprocal overflows, makes the refined reciprocal
+// NaN.  So the one class test of cfl_fold flags every non-physical cell.
 template <typename T, int D>
 __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double gamma) {
   double ud[D + 2];
@@ -271,9 +274,31 @@ __device__ __forceinline__ double cfl_q(const T* u, const double* inv_dx, double
   double q = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) q = fma(fabs(ud[1 + a]) + rc, inv_dx[a], q);
-  q *= ir;
-  const bool ok = (rho > 0.0) && (q < __builtin_huge_val());
-  return ok ? q : -1.0;
+  return q * ir;
+}
+
+// Floating-point class mask of everything but a positive finite number:
+// signalling and quiet NaN, -inf, negative normal and subnormal, -0, +0, +inf.
+constexpr int kNotPositiveFinite = 0x27F;
+
+// Fold one cell's CFL quantity into a lane's running maximum and its
+// non-physical flag: one class test and one maximum, which passes over NaN
+// and never prefers a non-positive value to a positive one.
+__device__ __forceinline__ void cfl_fold(double q, double& qmax, bool& bad) {
+  bad |= __builtin_amdgcn_class(q, kNotPositiveFinite);
+  qmax = fmax(qmax, q);
+}
+
+// The same for a wave whose lanes all evaluate q together, outside any
+// branch on which cells count (`valid`: a mask of those lanes): the flag is
+// a mask of lanes held in scalar registers, and the maximum runs on every
+// lane, so the caller drops the lanes outside `valid` when it commits.  The
+// one-stage 3D march runs faster this way (about 1% at 512^3); the 2D and
+// fused 3D marches run faster with cfl_fold inside their store branches.
+__device__ __forceinline__ void cfl_fold_wave(double q, unsigned long long valid, double& qmax,
+                                              unsigned long long& bad) {
+  bad |= __builtin_amdgcn_ballot_w64(__builtin_amdgcn_class(q, kNotPositiveFinite)) & valid;
+  qmax = fmax(qmax, q);
 }
 
 }  // namespace paraiso

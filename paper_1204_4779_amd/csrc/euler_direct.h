@@ -100,9 +100,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_direct(Args
 #pragma unroll
       for (int q = 0; q < D + 2; ++q) Uout.f[q][gc] = out[q];
       if (a.cfl && active) {
-        const double q = cfl_q<T, D>(out, M.inv_dx, M.gamma);
-        bad |= !(q > 0.0);
-        qmax = fmax(qmax, q);
+        cfl_fold(cfl_q<T, D>(out, M.inv_dx, M.gamma), qmax, bad);
       }
     }
     if (a.cfl && active) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);
@@ -201,9 +199,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_direct(Args
 #pragma unroll
       for (int q = 0; q < D + 2; ++q) Uout.f[q][gc] = out[q];
       if (a.cfl && active) {
-        const double q = cfl_q<T, D>(out, M.inv_dx, M.gamma);
-        bad |= !(q > 0.0);
-        qmax = fmax(qmax, q);
+        cfl_fold(cfl_q<T, D>(out, M.inv_dx, M.gamma), qmax, bad);
       }
     }
     if (a.cfl && active) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);

@@ -310,9 +310,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_stage_lds(Args a,
             Uout.f[q][gc] = out[q];
           }
           if (a.cfl && active) {
-            const double q = cfl_q<T, D>(out, M.inv_dx, M.gamma);
-            bad |= !(q > 0.0);
-            qmax = fmax(qmax, q);
+            cfl_fold(cfl_q<T, D>(out, M.inv_dx, M.gamma), qmax, bad);
           }
         }
       }
@@ -439,9 +437,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_fused_lds(Args a,
             Uout.f[q][gc] = out[q];
           }
           if (a.cfl && active) {
-            const double q = cfl_q<T, D>(out, M.inv_dx, M.gamma);
-            bad |= !(q > 0.0);
-            qmax = fmax(qmax, q);
+            cfl_fold(cfl_q<T, D>(out, M.inv_dx, M.gamma), qmax, bad);
           }
         }
       }

@@ -211,9 +211,7 @@ struct StripMarch {
 #pragma unroll
       for (int q = 0; q < 4; ++q) *at(Uout.f[q] + ro, c) = u[q];
       if (cfl) {
-        const double qv = cfl_q<T, 2>(u, inv_dx, gamma);
-        bad |= !(qv > 0.0);
-        qmax = qv > qmax ? qv : qmax;
+        cfl_fold(cfl_q<T, 2>(u, inv_dx, gamma), qmax, bad);
       }
     }
   }

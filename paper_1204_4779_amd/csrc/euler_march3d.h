@@ -105,8 +105,9 @@ struct PlaneMarch {
   int vslot, gslot;
   RowPipe5<T> P;
   T u_nx[5], uh_nx[5], base_nx[5];
-  double qmax;
-  bool bad;
+  double qmax;  // every lane; only the stored ones count
+  unsigned long long bad;  // lanes that stored a non-physical cell
+  unsigned long long store_mask;  // lanes that store
 
   __device__ __forceinline__ unsigned hide(unsigned b) const {
     asm volatile("" : "+v"(b));
@@ -204,12 +205,8 @@ struct PlaneMarch {
         const unsigned ob = hide(own_bytes);
 #pragma unroll
         for (int q = 0; q < 5; ++q) *at(Uout.f[q] + zo * plane, ob) = out[q];
-        if (cfl) {
-          const double qv = cfl_q<T, 3>(out, inv_dx, gamma);
-          bad |= !(qv > 0.0);
-          qmax = qv > qmax ? qv : qmax;
-        }
       }
+      if (cfl) cfl_fold_wave(cfl_q<T, 3>(out, inv_dx, gamma), store_mask, qmax, bad);
     }
   }
 
@@ -311,10 +308,11 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
       S.vslot = 5 * NR * 64;
       S.gslot = 5 * (NW + 1) * 64;
       S.qmax = 0.0;
-      S.bad = false;
+      S.bad = 0;
+      S.store_mask = __builtin_amdgcn_ballot_w64(store_lane);
       S.run((z1 - z0) + 4);
-      qmax = S.qmax;
-      bad = S.bad;
+      qmax = store_lane ? S.qmax : 0.0;
+      bad = S.bad != 0;
       __syncthreads();  // LDS reuse by the next item
     }
     if (a.cfl && active && last_stage) cfl_commit(a, t.m, qmax, bad, s_red, (a.ring + 1) % 3);
@@ -478,11 +476,7 @@ struct FusedPlaneMarch {
           const unsigned ob = hide(own_bytes);
 #pragma unroll
           for (int q = 0; q < 5; ++q) *at(Uout.f[q] + zo, ob) = out[q];
-          if (cfl) {
-            const double qv = cfl_q<T, 3>(out, inv_dx, gamma);
-            bad |= !(qv > 0.0);
-            qmax = qv > qmax ? qv : qmax;
-          }
+          if (cfl) cfl_fold(cfl_q<T, 3>(out, inv_dx, gamma), qmax, bad);
         }
       }
     }

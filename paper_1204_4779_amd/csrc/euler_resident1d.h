@@ -123,9 +123,7 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
       for (int r = 0; r < kResidentPerThread; ++r) {
         const int i = tid + r * kResidentThreads;
         if (i < n) {
-          const double qi = cfl_q<T, 1>(u[r], M.inv_dx, M.gamma);
-          b |= !(qi > 0.0);
-          q = fmax(q, qi);
+          cfl_fold(cfl_q<T, 1>(u[r], M.inv_dx, M.gamma), q, b);
         }
       }
       // the block maximum (thread 0) and the non-physical flag reach every thread through LDS

@@ -147,6 +147,53 @@ def test_cfl_flags_nonpositive_pressure(dtype, ndim):
         s.close()
 
 
+def _corrupt(U, ndim, cell, kind):
+    """One non-physical cell of the given kind (rho <= 0, p <= 0 or a component
+    that is not finite)."""
+    E = (ndim + 1,) + cell
+    if kind == "rho_zero":
+        U[(0,) + cell] = 0.0
+    elif kind == "rho_negzero":
+        U[(0,) + cell] = -0.0
+    elif kind == "rho_negative_energy_negative":  # gamma rho p > 0 although rho < 0
+        U[(0,) + cell] = -1.0
+        for a in range(ndim):
+            U[(1 + a,) + cell] = 0.0
+        U[E] = -2.0
+    elif kind == "rho_inf":
+        U[(0,) + cell] = np.inf
+    elif kind == "energy_inf":
+        U[E] = np.inf
+    elif kind == "energy_neginf":
+        U[E] = -np.inf
+    elif kind == "momentum_inf":
+        U[(1,) + cell] = np.inf
+    elif kind == "momentum_nan":
+        U[(ndim,) + cell] = np.nan
+    else:
+        raise ValueError(kind)
+    return U
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("kind", ["rho_zero", "rho_negzero", "rho_negative_energy_negative", "rho_inf",
+                                  "energy_inf", "energy_neginf", "momentum_inf", "momentum_nan"])
+def test_cfl_flags_every_nonphysical_kind(dtype, ndim, kind):
+    # the CFL term flags a cell by one class test of its quantity (anything
+    # but a positive finite number); every kind the oracle reports must land
+    # there, in the first cell of a block and in one inside it
+    pr = inputs.random_state(ndim, SHAPES[ndim], seed=31)
+    for cell in ((0,) * ndim, tuple(min(3, n - 1) for n in reversed(SHAPES[ndim]))):
+        bad = _corrupt(pr.U.copy(), ndim, cell, kind)
+        with pytest.raises(FloatingPointError):
+            oracle.cfl_dt(oracle_mesh(pr), as_input(bad, dtype), 0.5)
+        s = gpu_solver(spec_of(pr), dtype, None, bad)
+        with pytest.raises(FloatingPointError):
+            s.cfl_dt(0.5)
+        s.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("ndim", [1, 2, 3])
 def test_totals_match_oracle(dtype, ndim):

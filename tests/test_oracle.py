@@ -335,6 +335,56 @@ def test_cfl_flags_nonphysical_state():
         oracle.cfl_dt(m, bad, 0.5)
 
 
+# Every kind of non-physical cell the CFL reduction must report (rho <= 0,
+# p <= 0, or a component that is not finite): each written into one cell.
+def _corrupt(U, ndim, cell, kind):
+    E = (ndim + 1,) + cell
+    if kind == "rho_zero":
+        U[(0,) + cell] = 0.0
+    elif kind == "rho_negzero":
+        U[(0,) + cell] = -0.0
+    elif kind == "rho_negative_energy_negative":  # rho E - |m|^2/2 > 0 although rho < 0
+        U[(0,) + cell] = -1.0
+        for a in range(ndim):
+            U[(1 + a,) + cell] = 0.0
+        U[E] = -2.0
+    elif kind == "rho_inf":
+        U[(0,) + cell] = np.inf
+    elif kind == "energy_inf":
+        U[E] = np.inf
+    elif kind == "energy_neginf":
+        U[E] = -np.inf
+    elif kind == "momentum_inf":
+        U[(1,) + cell] = np.inf
+    elif kind == "momentum_nan":
+        U[(ndim,) + cell] = np.nan
+    elif kind == "pressure_negative":
+        U[E] = 0.25 * sum(U[(1 + a,) + cell] ** 2 for a in range(ndim)) / U[(0,) + cell]
+    elif kind == "pressure_zero":
+        for a in range(ndim):
+            U[(1 + a,) + cell] = 0.0
+        U[E] = 0.0
+    else:
+        raise ValueError(kind)
+    return U
+
+
+NONPHYSICAL_KINDS = ["rho_zero", "rho_negzero", "rho_negative_energy_negative", "rho_inf", "energy_inf",
+                     "energy_neginf", "momentum_inf", "momentum_nan", "pressure_negative", "pressure_zero"]
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+@pytest.mark.parametrize("kind", NONPHYSICAL_KINDS)
+def test_cfl_flags_every_nonphysical_kind(ndim, kind):
+    shape = {1: (20,), 2: (8, 6), 3: (5, 4, 3)}[ndim]
+    pr = inputs.random_state(ndim, shape, seed=31)
+    m = _mesh(pr)
+    oracle.cfl_dt(m, pr.U, 0.5)  # the uncorrupted state is physical
+    bad = _corrupt(pr.U.copy(), ndim, (1,) * ndim, kind)
+    with pytest.raises(FloatingPointError):
+        oracle.cfl_dt(m, bad, 0.5)
+
+
 def test_midpoint_structure():
     # Time marching equations: U1 = AddFlux(dt/2, Flux(U0), U0), U2 = AddFlux(dt, Flux(U1), U0).
     pr = inputs.random_state(2, (10, 8), seed=4)
