@@ -119,23 +119,24 @@ struct PlaneMarch {
   }
   __device__ __forceinline__ int zoff(int k) const { return map_index(first + k, nz, bcz) * plane; }
 
-  // loads of push k (own row, halo row if its y-faces are needed, base of
-  // the plane assembled at push k)
-  __device__ __forceinline__ void load(int k, bool yp, int npush) {
+  // loads of push k: own row, halo row, and the base of the plane assembled
+  // at push k.  All unconditional (a wave without a halo row reloads its own
+  // row, a push that assembles no plane loads its input plane as the base),
+  // so that no register keeps an older load's value across a branch: such a
+  // merge would make the next push wait for the loads it has just issued.
+  // (Pointing the loads a push does not need at rows the cache holds saves
+  // traffic but measured slower.)
+  __device__ __forceinline__ void load(int k) {
     const int zo = zoff(k);
     const unsigned ob = hide(own_bytes);
 #pragma unroll
     for (int q = 0; q < 5; ++q) u_nx[q] = *at(Uin.f[q] + zo, ob);
-    if (has_halo && yp) {
-      const unsigned hb = hide(halo_bytes);
+    const unsigned hb = hide(halo_bytes);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) uh_nx[q] = *at(Uin.f[q] + zo, hb);
-    }
-    if (k >= 4) {
-      const int zb = (first + k - 2) * plane;  // assembled planes lie inside the mesh
+    for (int q = 0; q < 5; ++q) uh_nx[q] = *at(Uin.f[q] + zo, hb);
+    const int zb = k >= 4 ? (first + k - 2) * plane : zo;  // assembled planes lie inside the mesh
 #pragma unroll
-      for (int q = 0; q < 5; ++q) base_nx[q] = *at(U0.f[q] + zb, ob);
-    }
+    for (int q = 0; q < 5; ++q) base_nx[q] = *at(U0.f[q] + zb, ob);
   }
 
   // push k with V buffer VB = k mod 2 and y-flux slot GB = k mod 3 (compile
@@ -154,7 +155,7 @@ struct PlaneMarch {
       uh[q] = uh_nx[q];
       base[q] = base_nx[q];
     }
-    if (k + 1 < npush) load(k + 1, k + 1 >= 2 && k + 1 < npush - 2, npush);
+    if (k + 1 < npush) load(k + 1);
     prim_of_cons<T, 3>(u, v, g);
     T* Vs = sV + vb * vslot;
 #pragma unroll
@@ -213,7 +214,7 @@ struct PlaneMarch {
   __device__ __forceinline__ void run(int npush) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) uh_nx[q] = base_nx[q] = T(0);
-    load(0, false, npush);
+    load(0);
     int k = 0;
     // warm-up and short chunks: run-time phase
 #pragma clang loop unroll(disable)
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(512) PARAISO_WAVES_ATTR(W) k_march3d(Args a, L
       S.first = z0 - 2;
       S.bcz = M.bc[2];
       S.own_bytes = (unsigned)(yown * nx + col) * (unsigned)sizeof(T);
-      S.halo_bytes = (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T);
+      S.halo_bytes = has_halo ? (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T) : S.own_bytes;
       S.wave = wave;
       S.NW = NW;
       S.NR = NR;
@@ -380,27 +381,23 @@ struct FusedPlaneMarch {
   __device__ __forceinline__ int zoff(int k) const { return map_index(first + k, nz, kPeriodic) * plane; }
 
   // loads of push k: own row and halo row of plane k, the bases of the
-  // planes assembled in push k (stage 1: k - 2, stage 2: k - 5)
+  // planes assembled in push k (stage 1: k - 2, stage 2: k - 5).  All
+  // unconditional, as in the one-stage march (a wave without a halo row
+  // reloads its own row; planes wrap, so every index is valid).
   __device__ __forceinline__ void load(int k) {
     const unsigned ob = hide(own_bytes);
     const int zo = zoff(k);
 #pragma unroll
     for (int q = 0; q < 5; ++q) u_nx[q] = *at(U0.f[q] + zo, ob);
-    if (has_halo && k <= Z + 5) {
-      const unsigned hb = hide(halo_bytes);
+    const unsigned hb = hide(halo_bytes);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) uh_nx[q] = *at(U0.f[q] + zo, hb);
-    }
-    if (k >= 4) {
-      const int z1 = zoff(k - 2);
+    for (int q = 0; q < 5; ++q) uh_nx[q] = *at(U0.f[q] + zo, hb);
+    const int z1 = zoff(k - 2);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) b1_nx[q] = *at(U0.f[q] + z1, ob);
-    }
-    if (out_wave && k >= 9) {
-      const int z2 = zoff(k - 5);
+    for (int q = 0; q < 5; ++q) b1_nx[q] = *at(U0.f[q] + z1, ob);
+    const int z2 = zoff(k - 5);
 #pragma unroll
-      for (int q = 0; q < 5; ++q) b2_nx[q] = *at(U0.f[q] + z2, ob);
-    }
+    for (int q = 0; q < 5; ++q) b2_nx[q] = *at(U0.f[q] + z2, ob);
   }
 
   __device__ __forceinline__ void push(int k) {
@@ -594,7 +591,7 @@ __global__ void __launch_bounds__(sizeof(T) == 8 ? 384 : 768) PARAISO_WAVES_ATTR
       S.first = z0 - 4;
       S.Z = z1 - z0;
       S.own_bytes = (unsigned)(yown * nx + col) * (unsigned)sizeof(T);
-      S.halo_bytes = (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T);
+      S.halo_bytes = has_halo ? (unsigned)(yhalo * nx + col) * (unsigned)sizeof(T) : S.own_bytes;
       S.wave = wave;
       S.NW = NW;
       S.lane = lane;
