@@ -155,7 +155,7 @@ struct StripMarch {
   int lane;
   // analytic boundaries (AN, one stage): the stage's input ghost cells come
   // from the ghost arrays (exact solution at the time of the stage's input)
-  const T* gsrc;  // this stage's set, field 0
+  const __attribute__((address_space(1))) T* gsrc;  // this stage's set, field 0
   int gS;         // field stride of the ghost arrays
   int gx;         // lane's column + 2, clamped to [0, nx + 3]: its place in a ghost row
   int gxj;        // lane's ghost column 0..3 on an analytic x axis, else -1
@@ -177,30 +177,28 @@ struct StripMarch {
   }
 
   __device__ __forceinline__ void load_row(int k, T* u) const {
-    if constexpr (AN) {
-      const int r = first + k;
-      if (grows && (r < 0 || r >= ny)) {
-        int j = r < 0 ? r + 2 : r - ny + 2;  // ghost row 0..3 (clamped: the prefetch may run past)
-        j = j < 0 ? 0 : (j > 3 ? 3 : j);
-        const T* src = gsrc + 4 * (ny + 4) + j * (nx + 4) + gx;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = src[q * gS];
-        return;
-      }
-    }
-    const int ro = map_index(first + k, ny, bcy) * nx;
+    const int ro = map_index(first + k, ny, bcy) * nx;  // in range for any row
     const unsigned c = lane_bytes();
+    if constexpr (AN) {
+      // One load per field from a per-lane address: the mesh row, a ghost
+      // row (analytic y, a row outside the mesh) or the lane's ghost column
+      // (analytic x, a lane outside the mesh).  No branch: a value merged
+      // from two loads across a branch makes the wave wait at the merge for
+      // the newest of them.
+      const int r = first + k;
+      int j = r < 0 ? r + 2 : r - ny + 2;  // ghost row 0..3 (clamped: the prefetch may run past)
+      j = j < 0 ? 0 : (j > 3 ? 3 : j);
+      int rr = r + 2;
+      rr = rr < 0 ? 0 : (rr > ny + 3 ? ny + 3 : rr);
+      const bool grow = grows && (r < 0 || r >= ny);
+      const int goff = grow ? 4 * (ny + 4) + j * (nx + 4) + gx : (gxj < 0 ? 0 : gxj) * (ny + 4) + rr;
+      const bool ghost = grow || gxj >= 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) u[q] = *(ghost ? gsrc + goff + q * gS : at(Uin.f[q] + ro, c));
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) u[q] = *at(Uin.f[q] + ro, c);
-    if constexpr (AN) {
-      if (gxj >= 0) {
-        int rr = first + k + 2;
-        rr = rr < 0 ? 0 : (rr > ny + 3 ? ny + 3 : rr);
-        const T* src = gsrc + gxj * (ny + 4) + rr;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = src[q * gS];
-      }
-    }
   }
 
   __device__ __forceinline__ void emit(int y, const T* u) {
@@ -396,7 +394,8 @@ __global__ void __launch_bounds__(256) PARAISO_WAVES_ATTR(W) k_march2d(Args a, L
       S.lane = lane;
       if constexpr (AN) {
         S.gS = ghost_stride(nx, ny);
-        S.gsrc = reinterpret_cast<const T*>(M.ghost) + (a.stage == 2 ? 4 * S.gS : 0);
+        S.gsrc = (const __attribute__((address_space(1))) T*)(reinterpret_cast<const T*>(M.ghost) +
+                                                              (a.stage == 2 ? 4 * S.gS : 0));
         const int xc = x0 - H + lane;
         int gj = xc < 0 ? xc + 2 : xc - nx + 2;
         gj = gj < 0 ? 0 : (gj > 3 ? 3 : gj);
