@@ -22,6 +22,24 @@ constexpr int kResidentThreads = 1024;
 constexpr int kResidentPerThread = 4;
 constexpr int kResidentCells = kResidentThreads * kResidentPerThread;
 
+// HLLC flux of face f (between cells f-1 and f) from the primitives in LDS.
+template <typename T>
+__device__ __forceinline__ void resident_face(const MeshDev& M, const Gas<T>& g, int n, const T* sV, int f,
+                                              T* fl) {
+  const int i0 = map_index(f - 2, n, M.bc[0]), i1 = map_index(f - 1, n, M.bc[0]);
+  const int i2 = map_index(f, n, M.bc[0]), i3 = map_index(f + 1, n, M.bc[0]);
+  T vl[3], vr[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const T* y = sV + q * n;
+    face_states(y[i0], y[i1], y[i2], y[i3], vl[q], vr[q]);
+  }
+  hllc<T, 1, 0>(vl, vr, fl, g);
+}
+
+// One stage over the resident mesh.  No barrier at the end: the next stage
+// first writes sV, which every thread has finished reading at the barrier
+// after the flux phase, and writes sF only after its own first barrier.
 template <typename T>
 __device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g, int n, T coef,
                                                const T (*uin)[3], const T (*ubase)[3], T (*uout)[3], T* sV,
@@ -39,19 +57,26 @@ __device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g
     }
   }
   __syncthreads();
-  // face f lies between cells f-1 and f (f = 0..n)
-  for (int f = tid; f <= n; f += kResidentThreads) {
-    const int i0 = map_index(f - 2, n, M.bc[0]), i1 = map_index(f - 1, n, M.bc[0]);
-    const int i2 = map_index(f, n, M.bc[0]), i3 = map_index(f + 1, n, M.bc[0]);
-    T vl[3], vr[3], fl[3];
+  // faces f = 0..n: thread t takes t, t + kResidentThreads, ...  A wave with
+  // a lane that holds two faces in one round evaluates both in one pass (two
+  // independent chains), so the (n + 1)-th face of a mesh of a multiple of
+  // kResidentThreads cells does not cost a round of its own.
+  for (int f0 = tid; f0 <= n; f0 += 2 * kResidentThreads) {
+    const int f1 = f0 + kResidentThreads;
+    T fa[3];
+    if (__builtin_amdgcn_ballot_w64(f1 <= n)) {
+      T fb[3];
+      resident_face<T>(M, g, n, sV, f0, fa);
+      resident_face<T>(M, g, n, sV, f1 <= n ? f1 : f0, fb);
+      if (f1 <= n) {
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T* y = sV + q * n;
-      face_states(y[i0], y[i1], y[i2], y[i3], vl[q], vr[q]);
+        for (int q = 0; q < 3; ++q) sF[q * (n + 1) + f1] = fb[q];
+      }
+    } else {
+      resident_face<T>(M, g, n, sV, f0, fa);
     }
-    hllc<T, 1, 0>(vl, vr, fl, g);
 #pragma unroll
-    for (int q = 0; q < 3; ++q) sF[q * (n + 1) + f] = fl[q];
+    for (int q = 0; q < 3; ++q) sF[q * (n + 1) + f0] = fa[q];
   }
   __syncthreads();
 #pragma unroll
@@ -65,14 +90,12 @@ __device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g
       }
     }
   }
-  __syncthreads();  // sV / sF are rewritten by the next stage
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double s_red[16];
-  __shared__ int s_bad;
+  __shared__ double s_red[kResidentThreads / 64];
   const int m = blockIdx.x;
   const MeshDev& M = a.meshes[m];
   const int n = M.n[0];
@@ -117,6 +140,9 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     t += dt;
     ++steps;
     if (!explicit_dt) {
+      // CFL maximum of the new state, a non-physical cell counted as +inf:
+      // each wave reduces its lanes, one barrier, and every thread folds the
+      // waves' maxima itself (s_red is next written after two more barriers)
       double q = 0.0;
       bool b = false;
 #pragma unroll
@@ -126,17 +152,15 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
           cfl_fold(cfl_q<T, 1>(u[r], M.inv_dx, M.gamma), q, b);
         }
       }
-      // the block maximum (thread 0) and the non-physical flag reach every thread through LDS
-      const double bm = block_max(b ? -1.0 : q, s_red);
+      double v = b ? __builtin_huge_val() : q;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+      if ((tid & 63) == 0) s_red[tid >> 6] = v;
       __syncthreads();
-      if (tid == 0) s_red[0] = bm;
-      if (tid == 0) s_bad = 0;
-      __syncthreads();
-      if (b) s_bad = 1;
-      __syncthreads();
-      qmax = s_red[0];
-      bad = s_bad != 0;
-      __syncthreads();
+      v = s_red[0];
+      for (int k = 1; k < kResidentThreads / 64; ++k) v = fmax(v, s_red[k]);
+      bad = !(v < __builtin_huge_val());
+      qmax = v;
     }
   }
 #pragma unroll
