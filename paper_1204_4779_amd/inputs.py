@@ -247,6 +247,17 @@ def cold_stirred_2d(n: tuple, seed: int, amp: float, p0: float = 1e-3, gamma: fl
                    conserved(gamma, rho, vel, p))
 
 
+def cold_stirred_1d(n: int, seed: int, amp: float, p0: float = 1e-3, gamma: float = 1.4, bc: int = 0) -> Problem:
+    """The 1D line of `cold_stirred_2d`: rho = exp(0.3 g0), v = amp g1 exp(-(x - 0.5)^2 / 0.01),
+    p = p0."""
+    x = centres(n)
+    w = np.exp(-((x - 0.5) ** 2) / 0.01)
+    rho = np.exp(0.3 * gaussian(seed, 0, n))
+    vel = [amp * gaussian(seed, 1, n) * w]
+    p = np.full(n, float(p0))
+    return Problem("cold_stirred", 1, (n, 1, 1), gamma, (bc, 0, 0), conserved(gamma, rho, vel, p))
+
+
 # ----------------------------------------------------------------------------------------
 # the same generator in torch (any device): the large 3D boxes are generated where they
 # are used instead of on the host.  The uniforms are bit-identical to the numpy ones; the

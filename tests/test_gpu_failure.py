@@ -98,3 +98,29 @@ def test_batch_failing_mesh_stops_others_continue():
     assert max(field_errs(gpu_state(s, 0), ref_bad)) <= 1e-11
     assert max(field_errs(gpu_state(s, 1), ref_good)) <= 1e-11
     s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_resident_1d_advance_stops_at_the_failing_step(dtype):
+    """The resident 1D kernel (the whole advance in one launch, its own CFL
+    reduction per step): a cold stirred line of 200 cells (seed 14, amplitude
+    0.5, p = 1e-3) whose pressure goes negative in the output of step 2 (the
+    oracle's minimum pressure: 3.5e-4 after step 1, 9.1e-5 in step 2's
+    stage-1 state, -6.0e-5 after step 2)."""
+    pr = inputs.cold_stirred_1d(200, seed=14, amp=0.5)
+    U = as_input(pr.U, dtype)
+    ref, t_ref, k_ref, ok = oracle.advance(oracle_mesh(pr), U, 0.5, math.inf, max_steps=20, on_failure="return")
+    assert not ok and k_ref == 2
+    s = gpu_solver([spec_of(pr)], dtype, dict(tile=(200,), lds=3, fuse=1), pr.U)
+    print(f"resident failure advance: {dtype}", flush=True)
+    with pytest.raises(pb.NonFiniteError) as ei:
+        s.advance(math.inf, 0.5, max_steps=20)
+    assert ei.value.steps == [k_ref]
+    assert abs(ei.value.t[0] - t_ref) <= (1e-13 if dtype == "f64" else 1e-6) * t_ref
+    got = gpu_state(s)
+    assert max(field_errs(got, ref)) <= (1e-11 if dtype == "f64" else 2e-5)
+    with pytest.raises(pb.NonFiniteError) as ei2:
+        s.advance(math.inf, 0.5, max_steps=20, t0=ei.value.t)
+    assert ei2.value.steps == [0]
+    assert np.array_equal(gpu_state(s), got)
+    s.close()

@@ -385,6 +385,24 @@ def test_cfl_flags_every_nonphysical_kind(ndim, kind):
         oracle.cfl_dt(m, bad, 0.5)
 
 
+def test_cold_stirred_line_fails_in_step_two_with_margins():
+    # the input of the resident kernel's failure test: physical with wide
+    # margins up to step 2's stage-1 state, clearly non-physical after step 2
+    pr = inputs.cold_stirred_1d(200, seed=14, amp=0.5)
+    m = _mesh(pr)
+    U1s, _, k, ok = oracle.advance(m, pr.U, 0.5, math.inf, max_steps=1, on_failure="return")
+    assert ok and k == 1
+    dt = oracle.cfl_dt(m, U1s, 0.5)
+    U1 = oracle.stage(m, U1s, U1s, 0.5 * dt)
+    out = oracle.stage(m, U1, U1s, dt)
+
+    def pmin(U):
+        return float(np.min(0.4 * (U[2] - 0.5 * U[1] ** 2 / U[0])))
+    assert pmin(U1s) > 3e-4 and pmin(U1) > 8e-5 and pmin(out) < -5e-5
+    _, _, k2, ok2 = oracle.advance(m, pr.U, 0.5, math.inf, max_steps=20, on_failure="return")
+    assert not ok2 and k2 == 2
+
+
 def test_midpoint_structure():
     # Time marching equations: U1 = AddFlux(dt/2, Flux(U0), U0), U2 = AddFlux(dt, Flux(U1), U0).
     pr = inputs.random_state(2, (10, 8), seed=4)
