@@ -258,6 +258,23 @@ def cold_stirred_1d(n: int, seed: int, amp: float, p0: float = 1e-3, gamma: floa
     return Problem("cold_stirred", 1, (n, 1, 1), gamma, (bc, 0, 0), conserved(gamma, rho, vel, p))
 
 
+def cold_stirred_3d(n: tuple, seed: int, amp: float, p0: float = 1e-3, width: float = 0.04,
+                    gamma: float = 1.4) -> Problem:
+    """The periodic box analogue of `cold_stirred_2d`: rho = exp(0.3 g0),
+    v_a = amp g_{a+1} exp(-r^2 / width) with r the distance to the box centre, p = p0."""
+    nx, ny, nz = n
+    x = centres(nx)[None, None, :]
+    y = centres(ny)[None, :, None]
+    z = centres(nz)[:, None, None]
+    w = np.exp(-((x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2) / width)
+    shape = (nz, ny, nx)
+    count = nx * ny * nz
+    rho = np.exp(0.3 * gaussian(seed, 0, count).reshape(shape))
+    vel = [amp * gaussian(seed, 1 + a, count).reshape(shape) * w for a in range(3)]
+    p = np.full(shape, float(p0))
+    return Problem("cold_stirred", 3, (nx, ny, nz), gamma, (0, 0, 0), conserved(gamma, rho, vel, p))
+
+
 # ----------------------------------------------------------------------------------------
 # the same generator in torch (any device): the large 3D boxes are generated where they
 # are used instead of on the host.  The uniforms are bit-identical to the numpy ones; the

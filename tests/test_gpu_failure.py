@@ -124,3 +124,38 @@ def test_resident_1d_advance_stops_at_the_failing_step(dtype):
     assert ei2.value.steps == [0]
     assert np.array_equal(gpu_state(s), got)
     s.close()
+
+
+# (FP32 variant, FP64 variant): the FP64 LDS tiles hold fewer cells
+FAMILIES_3D = {
+    "march": (dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3),) * 2,
+    "march_fused": (dict(tile=(64, 12, 64), lds=2, fuse=1), dict(tile=(64, 6, 32), lds=2, fuse=1)),
+    "lds_fused": (dict(tile=(8, 8, 8), lds=1, fuse=1), dict(tile=(8, 4, 4), lds=1, fuse=1)),
+    "direct": (dict(tile=(16, 4, 4), lds=0, fuse=0),) * 2,
+}
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("family", sorted(FAMILIES_3D))
+def test_advance_3d_stops_at_the_failing_step(family, dtype):
+    """A periodic box 20 x 16 x 12 (cold stirred, seed 7, amplitude 0.3, p = 1e-3)
+    whose step 2 turns non-physical: the oracle's minimum pressure is 2.3e-4 after
+    step 1 and -2.1e-5 already in step 2's stage-1 state, so step 2's output is not
+    fixed by the scheme (a sound speed of a negative pressure), but both sides stop
+    after step 2, at the time step 1's state fixes."""
+    pr = inputs.cold_stirred_3d((20, 16, 12), seed=7, amp=0.3)
+    U = as_input(pr.U, dtype)
+    _, t_ref, k_ref, ok = oracle.advance(oracle_mesh(pr), U, 0.5, math.inf, max_steps=20, on_failure="return")
+    assert not ok and k_ref == 2
+    s = gpu_solver([spec_of(pr)], dtype, FAMILIES_3D[family][dtype == "f64"], pr.U)
+    print(f"3D failure advance: {family} {dtype}", flush=True)
+    with pytest.raises(pb.NonFiniteError) as ei:
+        s.advance(math.inf, 0.5, max_steps=20)
+    assert ei.value.steps == [k_ref]
+    assert abs(ei.value.t[0] - t_ref) <= (1e-13 if dtype == "f64" else 1e-6) * t_ref
+    got = gpu_state(s)
+    with pytest.raises(pb.NonFiniteError) as ei2:
+        s.advance(math.inf, 0.5, max_steps=20, t0=ei.value.t)
+    assert ei2.value.steps == [0]
+    assert np.array_equal(gpu_state(s), got, equal_nan=True)
+    s.close()

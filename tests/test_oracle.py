@@ -403,6 +403,23 @@ def test_cold_stirred_line_fails_in_step_two_with_margins():
     assert not ok2 and k2 == 2
 
 
+def test_cold_stirred_box_fails_in_step_two():
+    # the input of the 3D failure test: physical with a wide margin after step 1,
+    # non-physical from step 2's stage-1 state on
+    pr = inputs.cold_stirred_3d((20, 16, 12), seed=7, amp=0.3)
+    m = _mesh(pr)
+    U1s, _, k, ok = oracle.advance(m, pr.U, 0.5, math.inf, max_steps=1, on_failure="return")
+    assert ok and k == 1
+    dt = oracle.cfl_dt(m, U1s, 0.5)
+    U1 = oracle.stage(m, U1s, U1s, 0.5 * dt)
+
+    def pmin(U):
+        return float(np.min(0.4 * (U[4] - 0.5 * (U[1] ** 2 + U[2] ** 2 + U[3] ** 2) / U[0])))
+    assert pmin(U1s) > 2e-4 and pmin(U1) < -1e-5
+    _, _, k2, ok2 = oracle.advance(m, pr.U, 0.5, math.inf, max_steps=20, on_failure="return")
+    assert not ok2 and k2 == 2
+
+
 def test_midpoint_structure():
     # Time marching equations: U1 = AddFlux(dt/2, Flux(U0), U0), U2 = AddFlux(dt, Flux(U1), U0).
     pr = inputs.random_state(2, (10, 8), seed=4)
