@@ -358,11 +358,17 @@ __device__ __forceinline__ int find_mesh_chunk(const MeshDev* ms, int nm, int ch
   return lo;
 }
 
-// CFL maximum of the current state into qbits[ring]; one block per chunk of
-// kChunk cells in storage order.
+// CFL maximum of the current state into qbits[ring]; one block of 256
+// threads per chunk of kChunk cells in storage order.  A full chunk is read
+// with 16-byte loads (4 FP32 or 2 FP64 cells per load and field), all of a
+// thread's loads issued before its arithmetic; a mesh's last, partial chunk
+// (or a field array whose chunk start is not 16-byte aligned) cell by cell.
 template <typename T, int D>
 __global__ void __launch_bounds__(256) k_cfl(Args a) {
   __shared__ double s_red[16];
+  constexpr int V = 16 / (int)sizeof(T);        // cells per 16-byte load
+  constexpr int kIter = kChunk / (256 * V);     // loads per field and thread
+  static_assert(kChunk % (256 * V) == 0, "a chunk is a whole number of vector rounds");
   const int chunk = blockIdx.x;
   const int m = find_mesh_chunk(a.meshes, a.nmeshes, chunk);
   const MeshDev& M = a.meshes[m];
@@ -371,14 +377,37 @@ __global__ void __launch_bounds__(256) k_cfl(Args a) {
   const int c1 = min(c0 + kChunk, M.ncells);
   double qmax = 0.0;
   bool bad = false;
-  // four cells per thread in flight: the loads of the next iterations are
-  // issued before this one's arithmetic
-#pragma unroll 4
-  for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
-    T u[D + 2];
+  bool aligned = true;
 #pragma unroll
-    for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][c];
-    cfl_fold(cfl_q<T, D>(u, M.inv_dx, M.gamma), qmax, bad);
+  for (int q = 0; q < D + 2; ++q) aligned &= ((unsigned long long)(U.f[q] + c0) & 15ull) == 0;
+  if (c1 - c0 == kChunk && aligned) {
+    using Vec = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
+    Vec w[kIter][D + 2];
+#pragma unroll
+    for (int it = 0; it < kIter; ++it)
+#pragma unroll
+      for (int q = 0; q < D + 2; ++q)
+        w[it][q] = *reinterpret_cast<const __attribute__((address_space(1))) Vec*>(
+            U.f[q] + c0 + (it * 256 + (int)threadIdx.x) * V);
+#pragma unroll
+    for (int it = 0; it < kIter; ++it)
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        T u[D + 2];
+#pragma unroll
+        for (int q = 0; q < D + 2; ++q) u[q] = w[it][q][j];
+        cfl_fold(cfl_q<T, D>(u, M.inv_dx, M.gamma), qmax, bad);
+      }
+  } else {
+    // four cells per thread in flight: the loads of the next iterations are
+    // issued before this one's arithmetic
+#pragma unroll 4
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+      T u[D + 2];
+#pragma unroll
+      for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][c];
+      cfl_fold(cfl_q<T, D>(u, M.inv_dx, M.gamma), qmax, bad);
+    }
   }
   cfl_commit(a, m, qmax, bad, s_red, a.ring);
 }
