@@ -14,7 +14,8 @@ Prints one JSON line.  Besides the headline it reports (in `extra`) FP64 and
 the untuned (per-cell, unfused, no LDS) variant of the headline workload and
 the other configurations of the metric: Sod 1024 FP64 to t = 0.2 (time to
 solution), the 3D periodic box at 256^3 and 512^3 (FP32, tuned and untuned),
-and the batch of 512 uneven 2D meshes (FP32, tuned and untuned); the roofline
+and the batch of 512 uneven 2D meshes (FP32, tuned, the tuned kernel fed by
+the persistent work queues, and untuned); the roofline
 of the dominant kernel; and the FP64 CPU oracle timed on bounded samples on
 the host, serially and on all host cores.
 
@@ -320,8 +321,12 @@ def batch_entries(steps: int, warmup: int, untuned: bool = True) -> dict:
     r = run_gpu([p.U for p in probs], "f32", var, steps, warmup, specs=specs)
     out["f32_tuned"] = config_entry(r, cells, 2, "f32", var)
     out["f32_tuned"]["audit_drift"] = r["mass_energy_drift"]
+    # the same kernel fed by the persistent per-XCD work queues instead of the plain grid
+    qv = dict(var, persistent=1)
+    r = run_gpu([p.U for p in probs], "f32", qv, steps, warmup, specs=specs)
+    out["f32_persistent_queue"] = config_entry(r, cells, 2, "f32", qv)
     if untuned:
-        uv = dict(variants.UNTUNED_2D, persistent=1)
+        uv = dict(variants.UNTUNED_2D)
         r = run_gpu([p.U for p in probs], "f32", uv, max(steps // 4, 6), min(warmup, 12), specs=specs)
         out["f32_untuned"] = config_entry(r, cells, 2, "f32", uv)
     return out
@@ -452,7 +457,7 @@ def other_workload(name: str, steps: int, warmup: int, sizes=None, with_cpu: boo
     if name == "batch512":
         e = batch_entries(steps, warmup, untuned=False)
         return dict(e["f32_tuned"], workload="batch_512_uneven_2d_periodic_fp32", unit="cell-updates/s",
-                    dtype="f32", cells=e["cells"])
+                    dtype="f32", cells=e["cells"], persistent_queue=e["f32_persistent_queue"])
     if name == "wave":
         return wave_workload(with_cpu)
     if name == "manifest":

@@ -141,7 +141,8 @@ typedef struct paraiso_variant {
   int32_t fuse;
   int32_t waves_per_eu;
   int32_t threads;
-  int32_t persistent;  /* 1: grid of a few workgroups per CU pulling tiles from a queue */
+  int32_t persistent;  /* 1: grid of a few workgroups per CU pulling tiles from a queue;
+                          0: one workgroup per tile (the default, also for batches) */
   int32_t manifest;
 } paraiso_variant;
 

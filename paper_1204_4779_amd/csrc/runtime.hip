@@ -676,7 +676,12 @@ void lds_variant(int ndim, paraiso_variant* v) {
 //   2D: the fused register march when every mesh is periodic on both axes
 //       (FP32 20 rows x 4 waves, FP64 40 rows x 4 waves), else LDS tiles;
 //   3D: the register march, 4 rows x 64-plane chunks, at most 168 VGPRs.
-// Batches pull tiles from the persistent queue.
+// Batches take the plain grid too, one workgroup per tile: on the 512-mesh
+// batch it ran as fast as the persistent queue or faster for every family
+// (fused 2D march +4%, one-stage march +19%, LDS tile equal, per-cell +9%),
+// since the hardware starts a new workgroup as soon as one ends, while a
+// persistent workgroup waits out two barriers and a device-scope atomic
+// for every tile it pulls.
 void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) {
   const int d = meshes[0].ndim;
   const bool f64 = meshes[0].dtype == PARAISO_F64;
@@ -726,7 +731,6 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
     v->waves_per_eu = 3;
     v->threads = 256;
   }
-  if (count > 1) v->persistent = 1;
 }
 
 // The control-block area of the pinned staging buffer.
@@ -849,7 +853,6 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
     // a device with less LDS than gfx950: the LDS-tile family always applies
     lds_variant(c->ndim, &v);
     if (any_analytic(meshes, count)) v.fuse = 0;
-    if (count > 1) v.persistent = 1;
     rc = apply_variant(c, v);
   }
   if (rc) return bail(rc);

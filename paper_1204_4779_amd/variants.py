@@ -23,10 +23,10 @@ TUNED = {
     # 64-plane chunks, VGPRs capped at 168 (3 waves per SIMD)
     ("box256", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3),
     ("box512", "f32"): dict(tile=(64, 4, 64), lds=2, fuse=0, waves_per_eu=3),
-    # one persistent launch per step pulling (mesh, tile) items from the
-    # per-XCD queues; 32 rows per wave from a rows sweep (the same items on a
-    # plain one-block-per-item grid run 4% faster, 64.6-65.1 against 62.2 G)
-    ("batch512", "f32"): dict(tile=(64, 32), lds=2, fuse=1, waves_per_eu=0, threads=256, persistent=1),
+    # one launch per step over every (mesh, tile) item, one block per item on
+    # a plain grid mapped onto the XCDs; 32 rows per wave from a rows sweep
+    # (the persistent queue over the same items: 62.2-62.4 against 64.5-64.9 G)
+    ("batch512", "f32"): dict(tile=(64, 32), lds=2, fuse=1, waves_per_eu=0, threads=256, persistent=0),
     # the whole advance in one launch, one workgroup holding the 1024 cells
     ("sod1024", "f64"): dict(tile=(1024,), lds=3, fuse=1),
     # convergence tests with analytic boundaries, N <= 1024: the one-stage

@@ -111,7 +111,7 @@ def test_default_variant(lib):
     v = pb.paraiso_default_variant([_mesh(dtype=pb.F64)])
     assert (v.lds, tuple(v.tile), v.threads) == (2, (64, 40, 1), 256)
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, 1, 0))])
-    assert v.lds == 1 and v.fuse == 1 and v.persistent == 1
+    assert v.lds == 1 and v.fuse == 1 and v.persistent == 0   # batches: one workgroup per tile
     # 3D: the one-stage register march
     v3 = pb.paraiso_default_variant([_mesh(3, (4, 4, 4))])
     assert (v3.lds, v3.fuse, tuple(v3.tile), v3.waves_per_eu) == (2, 0, (64, 4, 64), 3)
@@ -121,7 +121,7 @@ def test_default_variant(lib):
     assert pb.paraiso_default_variant([_mesh(1, (3407, 1, 1), pb.F64)]).lds == 3
     assert pb.paraiso_default_variant([_mesh(1, (3408, 1, 1), pb.F64)]).lds == 1
     v1 = pb.paraiso_default_variant([_mesh(1, (100, 1, 1)), _mesh(1, (1000, 1, 1))])
-    assert (v1.lds, v1.tile[0], v1.persistent) == (3, 1000, 1)
+    assert (v1.lds, v1.tile[0], v1.persistent) == (3, 1000, 0)
     # the march kernels take 32-bit byte offsets within a row (2D) / plane (3D)
     assert pb.paraiso_default_variant([_mesh(2, (1 << 29, 2, 1))]).lds == 2
     assert pb.paraiso_default_variant([_mesh(2, (1 << 30, 1, 1))]).lds == 1
@@ -134,7 +134,7 @@ def test_default_variant(lib):
         v = pb.paraiso_default_variant([_mesh(d, n, bc=(pb.ANALYTIC, 0, 0))])
         assert (v.lds, v.fuse) == ((2, 0) if d == 2 else (1, 0)), d
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, pb.ANALYTIC, 0))])
-    assert (v.lds, v.fuse, v.persistent, tuple(v.tile)) == (2, 0, 1, (64, 8, 1))
+    assert (v.lds, v.fuse, v.persistent, tuple(v.tile)) == (2, 0, 0, (64, 8, 1))
     v = pb.paraiso_default_variant([_mesh(dtype=pb.F64, bc=(pb.ANALYTIC,) * 3)])
     assert (tuple(v.tile), v.waves_per_eu) == ((64, 8, 1), 3)   # FP64: capped at 3 waves per SIMD
     # first-order reconstruction: the LDS-tile kernels (fused unless analytic)

@@ -100,6 +100,12 @@ def test_batch512_full():
     print(f"  batch512 strict {worst:.3e} (mesh {worst_k}, n={probs[worst_k].n[0]}, per field {worst_f}); "
           f"state-scaled with pointwise rho, E {worst_state:.3e}", flush=True)
     assert worst_state <= TOL["f32"]
+    # the same kernel fed by the persistent work queues: bitwise the plain grid's step
+    print("case batch512 f32 persistent queue", flush=True)
+    q = gpu_solver(specs, "f32", dict(variants.tuned("batch512", "f32"), persistent=1), [p.U for p in probs])
+    q.step(dts)
+    for k in range(len(probs)):
+        assert np.array_equal(gpu_state(q, k), gpu_state(s, k)), k
 
 
 def box512_planes(chunk: int) -> list:
