@@ -20,7 +20,10 @@
  * and the workspace), keeps them alive for the lifetime of the context, and
  * frees them after paraiso_destroy.  The library never allocates or frees
  * device memory.  It never aborts: every entry point returns a status code
- * and, on failure, leaves a message for paraiso_last_error().
+ * and, on failure, leaves a message for paraiso_last_error().  A HIP call of
+ * the library that fails is reported as PARAISO_ERR_HIP and taken off HIP's
+ * per-thread error record (hipGetLastError), so the caller's next HIP call
+ * does not report it again.
  *
  * Streams: a context is bound to the HIP stream given at init and is not
  * thread-safe; calls on one context must come from one thread at a time.
@@ -142,7 +145,10 @@ typedef struct paraiso_variant {
   int32_t waves_per_eu;
   int32_t threads;
   int32_t persistent;  /* 1: grid of a few workgroups per CU pulling tiles from a queue;
-                          0: one workgroup per tile (the default, also for batches) */
+                          0: one workgroup per tile (the default, also for batches),
+                          unless that grid would pass 2^32 work-items (rows of
+                          very few rows, tiny tiles): then the queue, and
+                          paraiso_get_variant reports 1 */
   int32_t manifest;
 } paraiso_variant;
 

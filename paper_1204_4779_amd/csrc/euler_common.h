@@ -374,13 +374,13 @@ __global__ void __launch_bounds__(256) k_cfl(Args a) {
   const MeshDev& M = a.meshes[m];
   const Fields<T, D> U = fields<T, D>(M.s[a.src]);
   const int c0 = (chunk - M.chunk0) * kChunk;
-  const int c1 = min(c0 + kChunk, M.ncells);
+  const int n = min(kChunk, M.ncells - c0);  // cells of this chunk (c0 + kChunk may pass 2^31 - 1)
   double qmax = 0.0;
   bool bad = false;
   bool aligned = true;
 #pragma unroll
   for (int q = 0; q < D + 2; ++q) aligned &= ((unsigned long long)(U.f[q] + c0) & 15ull) == 0;
-  if (c1 - c0 == kChunk && aligned) {
+  if (n == kChunk && aligned) {
     using Vec = __attribute__((ext_vector_type(16 / sizeof(T)))) T;
     Vec w[kIter][D + 2];
 #pragma unroll
@@ -402,10 +402,10 @@ __global__ void __launch_bounds__(256) k_cfl(Args a) {
     // four cells per thread in flight: the loads of the next iterations are
     // issued before this one's arithmetic
 #pragma unroll 4
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) {
+    for (int i = (int)threadIdx.x; i < n; i += blockDim.x) {
       T u[D + 2];
 #pragma unroll
-      for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][c];
+      for (int q = 0; q < D + 2; ++q) u[q] = U.f[q][c0 + i];
       cfl_fold(cfl_q<T, D>(u, M.inv_dx, M.gamma), qmax, bad);
     }
   }
@@ -424,13 +424,13 @@ __global__ void __launch_bounds__(256) k_totals_partial(Args a) {
   const MeshDev& M = a.meshes[m];
   const Fields<T, D> U = fields<T, D>(M.s[a.src]);
   const int c0 = (chunk - M.chunk0) * kChunk;
-  const int c1 = min(c0 + kChunk, M.ncells);
+  const int n = min(kChunk, M.ncells - c0);  // cells of this chunk (c0 + kChunk may pass 2^31 - 1)
   double s[D + 2];
 #pragma unroll
   for (int q = 0; q < D + 2; ++q) s[q] = 0.0;
-  for (int c = c0 + (int)threadIdx.x; c < c1; c += 256) {
+  for (int i = (int)threadIdx.x; i < n; i += 256) {
 #pragma unroll
-    for (int q = 0; q < D + 2; ++q) s[q] += (double)U.f[q][c];
+    for (int q = 0; q < D + 2; ++q) s[q] += (double)U.f[q][c0 + i];
   }
 #pragma unroll
   for (int q = 0; q < D + 2; ++q) s_sum[q][threadIdx.x] = s[q];

@@ -38,11 +38,17 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
-#define HIP_TRY(call)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(PARAISO_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+// A HIP call of the library failed: report it, and take the error off HIP's
+// per-thread record so that the caller's next HIP call does not see it again.
+int hip_fail(const std::string& what, hipError_t e) {
+  (void)hipGetLastError();
+  return fail(PARAISO_ERR_HIP, what + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                \
+  do {                                               \
+    hipError_t e_ = (call);                          \
+    if (e_ != hipSuccess) return hip_fail(#call, e_); \
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -335,12 +341,12 @@ int capture_graph(paraiso_ctx* c, int phase) {
     if (g) hipGraphDestroy(g);
     return rc;
   }
-  if (e != hipSuccess) return fail(PARAISO_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail("hipStreamEndCapture", e);
   e = hipGraphInstantiate(&c->graph[phase], g, nullptr, nullptr, 0);
   hipGraphDestroy(g);
   if (e != hipSuccess) {
     c->graph[phase] = nullptr;
-    return fail(PARAISO_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    return hip_fail("hipGraphInstantiate", e);
   }
   return PARAISO_OK;
 }
@@ -594,7 +600,10 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   L.shmem = shmem;
   L.with_geom = true;
   if (shmem > 65536) HIP_TRY(hipFuncSetAttribute(L.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem));
-  // grid
+  // grid: one workgroup per item, unless that grid passes the launch limit of
+  // 2^32 work-items (very long rows of very few rows, tiny tiles): then the
+  // persistent queue, which takes any number of items
+  if (v.lds != 3 && (int64_t)nitems * threads >= (int64_t(1) << 32)) v.persistent = 1;
   int grid = nitems;
   if (v.persistent) {
     int per_cu = 0;
@@ -812,7 +821,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
   c->pin_ctl = align256((L.dt - L.params) + sizeof(double) * count);
   if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_pin, c->pin_ctl + sizeof(Ctl) * count, hipHostMallocDefault);
-  if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("device query: ") + hipGetErrorString(e)));
+  if (e != hipSuccess) return bail(hip_fail("device query", e));
   // host mesh table
   c->hm.resize(count);
   size_t u1off = L.u1;
@@ -843,7 +852,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
     M.vol = vol;
     M.ncells = (int)cells_of(pm);
     M.chunk0 = chunk;
-    M.nchunks = (M.ncells + kChunk - 1) / kChunk;
+    M.nchunks = (int)(((int64_t)M.ncells + kChunk - 1) / kChunk);  // ncells + kChunk - 1 may pass 2^31 - 1
     chunk += M.nchunks;
   }
   paraiso_variant v;
@@ -859,7 +868,7 @@ int32_t paraiso_init(const paraiso_mesh* meshes, int32_t count, void* workspace,
   rc = ctl_init(c, nullptr);
   if (rc) return bail(rc);
   e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return bail(fail(PARAISO_ERR_HIP, std::string("init: ") + hipGetErrorString(e)));
+  if (e != hipSuccess) return bail(hip_fail("init", e));
   c->ctl_ready = true;
   c->analytic_set.assign(count, 0);
   *out = c;

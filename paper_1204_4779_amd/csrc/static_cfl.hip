@@ -46,6 +46,12 @@ int fail(int code, const char* msg) {
   return code;
 }
 
+// A HIP call failed: report it and take it off HIP's per-thread error record.
+int hip_fail(hipError_t e) {
+  (void)hipGetLastError();
+  return fail(PARAISO_ERR_HIP, hipGetErrorString(e));
+}
+
 // The device address of this device's scratch, looked up once per device
 // with that device current.
 int scratch_address(int device, unsigned char** out) {
@@ -55,8 +61,7 @@ int scratch_address(int device, unsigned char** out) {
     void* p = nullptr;
     const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess || !p) {
-      paraiso_set_error_text(hipGetErrorString(e));
-      return PARAISO_ERR_HIP;
+      return e != hipSuccess ? hip_fail(e) : fail(PARAISO_ERR_HIP, "hipGetSymbolAddress gave no address");
     }
     g_scratch_ptr[device] = static_cast<unsigned char*>(p);
   }
@@ -115,7 +120,7 @@ extern "C" int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t cou
 
   int device = 0;
   hipError_t e = hipGetDevice(&device);
-  if (e != hipSuccess) return fail(PARAISO_ERR_HIP, hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(e);
   unsigned char* base = nullptr;
   if (int rc = scratch_address(device, &base)) return rc;
   MeshDev* d_table = reinterpret_cast<MeshDev*>(base);
@@ -140,13 +145,13 @@ extern "C" int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t cou
     M.inv_gm1 = 1.0 / (pm.gamma - 1.0);
     M.ncells = (int)(pm.n[0] * pm.n[1] * pm.n[2]);
     M.chunk0 = chunks;
-    M.nchunks = (M.ncells + kChunk - 1) / kChunk;
+    M.nchunks = (int)(((int64_t)M.ncells + kChunk - 1) / kChunk);  // ncells + kChunk - 1 may pass 2^31 - 1
     chunks += M.nchunks;
   }
   e = hipMemcpyAsync(d_table, h_table, sizeof(MeshDev) * count, hipMemcpyHostToDevice, stream);
   // the control blocks start at zero: the last call's maxima and flags stay in scratch
   if (e == hipSuccess) e = hipMemsetAsync(d_ctl, 0, sizeof(Ctl) * count, stream);
-  if (e != hipSuccess) return fail(PARAISO_ERR_HIP, hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(e);
 
   Args a;
   std::memset(&a, 0, sizeof(a));
@@ -160,7 +165,7 @@ extern "C" int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t cou
   Ctl h_ctl[PARAISO_STATIC_MESHES];
   if (e == hipSuccess) e = hipMemcpyAsync(h_ctl, d_ctl, sizeof(Ctl) * count, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) return fail(PARAISO_ERR_HIP, hipGetErrorString(e));
+  if (e != hipSuccess) return hip_fail(e);
   for (int m = 0; m < count; ++m) {
     double q;
     std::memcpy(&q, &h_ctl[m].qbits[0], sizeof(q));

@@ -156,6 +156,7 @@ const void* wave_kernel(int64_t max_cells) {
 }
 
 int wave_fail(int code, const std::string& msg) {
+  if (code == PARAISO_ERR_HIP) (void)hipGetLastError();  // not left for the caller's next HIP call
   paraiso_set_error(msg);
   return code;
 }
