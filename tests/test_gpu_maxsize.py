@@ -6,6 +6,7 @@ Each case fills a seeded rough state on the device (density and pressure in
 [0.5, 2], velocities in [-1.5, 1.5]) with one planted high-pressure cell
 (p = 100 at rest, rho = 1) near the mesh's last cell, so the CFL maximum is
 known to lie in a window the oracle can evaluate. It then checks:
+  * the conserved totals: equal to FP64 sums of the fields taken by torch;
   * dt: the library's CFL step equals the oracle's on that window (the
     planted cell's q = d c = d sqrt(140), at least 23.6, exceeds every other
     cell's, at most d (1.5 + sqrt(5.6)) < 11.7, by construction);
@@ -125,6 +126,12 @@ def _check(s, ndim, dtype, windows, planted_at, families, seed):
     _plant_cell(st, planted_at, ndim)
     u0 = st.clone()
     torch.cuda.synchronize()
+    # conserved totals (unit cells) against torch's FP64 sums of the same fields
+    print(f"  totals over {np.prod(tuple(st.shape[1:]))} cells", flush=True)
+    tot = s.totals()[0]
+    for q in range(ndim + 2):
+        want = float(st[q].double().sum())
+        assert abs(tot[q] - want) <= 1e-11 * abs(want), (q, tot[q], want)
 
     # oracle windows of the input, and their one-step references
     wins = []
