@@ -211,7 +211,10 @@ int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
 /*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the CFL
- * time step of paraiso_cfl_dt without a context or workspace.
+ * time step of paraiso_cfl_dt without a context or workspace.  The call
+ * returns dt to the host, so it synchronizes and is not itself recorded
+ * into a graph; it allocates nothing, and clears its control blocks with a
+ * kernel rather than a memset.
  * dt_out[m] = cfl / max_i sum_a (|v_a| + c)/dx_a over the state in buffer
  * `buffer` (0 or 1) of meshes[m], in FP64, for 1 <= count <=
  * PARAISO_STATIC_MESHES meshes that share ndim and dtype; it reads ndim,

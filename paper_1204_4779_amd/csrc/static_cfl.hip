@@ -46,6 +46,14 @@ int fail(int code, const char* msg) {
   return code;
 }
 
+// Zero n 8-byte words: the control blocks are cleared by an ordinary kernel
+// launch on the caller's stream, not a memset.
+static_assert(sizeof(Ctl) % 8 == 0, "control blocks are whole 8-byte words");
+__global__ void __launch_bounds__(256) k_zero_words(unsigned long long* p, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = 0ull;
+}
+
 // A HIP call failed: report it and take it off HIP's per-thread error record.
 int hip_fail(hipError_t e) {
   (void)hipGetLastError();
@@ -149,8 +157,12 @@ extern "C" int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t cou
     chunks += M.nchunks;
   }
   e = hipMemcpyAsync(d_table, h_table, sizeof(MeshDev) * count, hipMemcpyHostToDevice, stream);
+  if (e != hipSuccess) return hip_fail(e);
   // the control blocks start at zero: the last call's maxima and flags stay in scratch
-  if (e == hipSuccess) e = hipMemsetAsync(d_ctl, 0, sizeof(Ctl) * count, stream);
+  const int words = (int)(sizeof(Ctl) * count / 8);
+  hipLaunchKernelGGL(k_zero_words, dim3((words + 255) / 256), dim3(256), 0, stream,
+                     reinterpret_cast<unsigned long long*>(d_ctl), words);
+  e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e);
 
   Args a;

@@ -146,6 +146,9 @@ def _check(s, ndim, dtype, windows, planted_at, families, seed):
     print(f"  cfl_dt over {np.prod(shape)} cells", flush=True)
     dt = s.cfl_dt(0.5)[0]
     assert abs(dt - dt_ref) <= 1e-14 * dt_ref, (dt, dt_ref)
+    # the entry point without a context runs the same reduction
+    stream = torch.cuda.current_stream().cuda_stream
+    assert pb.paraiso_cfl_dt_static(s.meshes, s.current(), 0.5, stream) == [dt]
     refs = [_interior(oracle.step(m, U, dt_ref), lo_hi) for lo_hi, U, m in wins]
     for (lo_hi, U, _), ref in zip(wins, refs):
         assert rel_err(ref, _interior(U, lo_hi)) > 1e-4      # the step changes every window
