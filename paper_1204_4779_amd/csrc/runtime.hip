@@ -481,7 +481,10 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
   // (the fused 3D march runs one wave per stage-1 row, up to 768 threads; its own check below)
   const bool fused3d = v.lds == 2 && c->ndim == 3 && v.fuse;
-  if (v.threads != 0 && !fused3d && (v.threads < 64 || v.threads > 512 || v.threads % 64))
+  // the resident kernel always runs one workgroup of kResidentThreads per
+  // mesh, the count paraiso_get_variant reports; it ignores other counts
+  const bool resident_count = v.lds == 3 && v.threads == kResidentThreads;
+  if (v.threads != 0 && !fused3d && !resident_count && (v.threads < 64 || v.threads > 512 || v.threads % 64))
     return why = "threads must be 0 or a multiple of 64 in [64, 512]", PARAISO_ERR_UNSUPPORTED;
   const int64_t tc = (int64_t)v.tile[0] * v.tile[1] * v.tile[2];
   if (tc > (1 << 22)) return why = "tile has more than 2^22 cells", PARAISO_ERR_UNSUPPORTED;
@@ -717,6 +720,7 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
       v->lds = 3;
       v->fuse = 1;
       v->tile[0] = (int32_t)nmax;
+      v->threads = kResidentThreads;
     }
   } else if (!march_offsets_fit(meshes, count)) {
     // rows or planes beyond the march kernels' 32-bit offsets: LDS tiles

@@ -293,6 +293,36 @@ def test_batch_advance_per_mesh_dt():
         assert rel_err(gpu_state(b, k), ref) < 1e-11
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_variant_round_trips(dtype):
+    # whatever paraiso_get_variant reports, paraiso_set_variant takes back unchanged:
+    # the library's defaults for every family and a few explicit choices
+    P, O, A = pb.PERIODIC, pb.OUTFLOW, pb.ANALYTIC
+    cases = [([pb.MeshSpec(1, (300,), 1.4, (O,))], None),                     # resident
+             ([pb.MeshSpec(1, (300,), 1.4, (P,)), pb.MeshSpec(1, (70,), 1.4, (O,))], None),
+             ([pb.MeshSpec(1, (5000,), 1.4, (P,))], None),                    # LDS tiles
+             ([pb.MeshSpec(2, (70, 50), 1.4, (P, P))], None),                 # fused march
+             ([pb.MeshSpec(2, (70, 50), 1.4, (O, P))], None),                 # LDS tiles
+             ([pb.MeshSpec(2, (70, 50), 1.4, (A, P))], None),                 # one-stage march, ghosts
+             ([pb.MeshSpec(2, (70, 50), 1.4, (P, P), order=1)], None),        # first order
+             ([pb.MeshSpec(3, (40, 20, 10), 1.4, (P, O, P))], None),          # 3D march
+             ([pb.MeshSpec(3, (40, 20, 10), 1.4, (P, P, P))], dict(tile=(64, 6, 16), lds=2, fuse=1)),
+             ([pb.MeshSpec(2, (70, 50), 1.4, (P, P))], dict(tile=(32, 16), lds=1, fuse=1, manifest=2)),
+             ([pb.MeshSpec(2, (70, 50), 1.4, (P, P))], dict(tile=(64, 4), lds=0, fuse=0, persistent=1))]
+    for specs, v in cases:
+        s = pb.Solver(specs, dtype)
+        if v is not None:
+            s.set_variant(v)
+        else:   # init applied the library's default, not a fallback
+            dv = pb.paraiso_default_variant(s.meshes).as_dict()
+            assert {k: s.variant()[k] for k in dv if k != "threads"} == \
+                {k: dv[k] for k in dv if k != "threads"}, (specs, dv, s.variant())
+        got = s.variant()
+        s.set_variant(got)
+        assert s.variant() == got, (specs, got, s.variant())
+        s.close()
+
+
 def test_set_variant_rejects_oversized_lds():
     pr = inputs.random_state(3, (16, 16, 16), seed=1)
     s = gpu_solver(spec_of(pr), "f64", None, pr.U)
