@@ -188,7 +188,8 @@ int32_t paraiso_get_variant(const paraiso_ctx* ctx, paraiso_variant* v);
  * workgroup, else LDS tiles; 2D the fused register march when every mesh is
  * periodic on both axes, else LDS tiles; 3D the register march.  Any mesh
  * with an analytic axis: in 2D the one-stage register march, else unfused
- * LDS tiles; first order: LDS tiles. */
+ * LDS tiles; first order: LDS tiles.  One workgroup per tile (persistent =
+ * 0), batches included. */
 int32_t paraiso_default_variant(const paraiso_mesh* meshes, int32_t count, paraiso_variant* v);
 
 /*
