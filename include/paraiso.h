@@ -222,7 +222,7 @@ int32_t paraiso_cfl_dt(paraiso_ctx* ctx, double cfl, double* dt_out);
  * dtype, n, dx, gamma and state[buffer] of each descriptor (bc and order do
  * not enter the CFL term).  Results equal paraiso_cfl_dt's bit for bit (same
  * reduction kernel).  The mesh table and the reduction's control blocks live
- * in a fixed device array of the library (at most 32 KiB per device, held
+ * in a fixed device array of the library (at most 48 KiB per device, held
  * until the process ends); nothing is allocated on the host or the device.
  * Every call on a device shares that device's array, so calls that overlap
  * on one device (other threads, other streams) race.  Synchronous on

@@ -62,13 +62,30 @@ struct MeshDev {
 // on each side for every column from -2 to nx+1 (4 (nx+4) cells).
 __host__ __device__ constexpr int ghost_stride(int nx, int ny) { return 4 * (ny + 4) + 4 * (nx + 4); }
 
+// The CFL maximum of a ring slot lives in kQSub sub-slots: block b folds its
+// maximum into sub-slot b mod kQSub (for 8, the XCD the block runs on), so
+// the one atomic per block of a launch spreads over kQSub addresses instead
+// of queueing on one when the blocks end together; readers take the largest
+// sub-slot (bit patterns of non-negative doubles order as unsigned integers).
+constexpr int kQSub = 8;
+
 struct Ctl {
   double t[3];
-  unsigned long long qbits[3];
+  unsigned long long qbits[3][kQSub];
   long long steps[3];
   int flags[3];  // per ring slot: bit 0 set when the state of that slot is non-physical or non-finite
   int pad_;
 };
+
+__host__ __device__ inline unsigned long long qbits_max(const Ctl& c, int slot) {
+  unsigned long long b = c.qbits[slot][0];
+  for (int k = 1; k < kQSub; ++k) b = c.qbits[slot][k] > b ? c.qbits[slot][k] : b;
+  return b;
+}
+
+__host__ __device__ inline void qbits_clear(Ctl& c, int slot) {
+  for (int k = 0; k < kQSub; ++k) c.qbits[slot][k] = 0ull;
+}
 
 struct Params {
   double t_end;
@@ -186,7 +203,7 @@ __device__ __forceinline__ double step_dt(const Args& a, int m, bool& active) {
   const long long st = c.steps[a.ring];
   active = (t < a.prm->t_end) && (st < a.prm->max_steps) && c.flags[a.ring] == 0;
   if (!active) return 0.0;
-  double dt = a.prm->cfl / __longlong_as_double((long long)c.qbits[a.ring]);
+  double dt = a.prm->cfl / __longlong_as_double((long long)qbits_max(c, a.ring));
   if (dt > a.prm->t_end - t) dt = a.prm->t_end - t;
   return dt;
 }
@@ -199,7 +216,7 @@ __device__ __forceinline__ void step_bookkeeping(const Args& a, int m, double dt
   // boundaries read the time)
   c.t[nx] = active ? c.t[a.ring] + dt : c.t[a.ring];
   c.steps[nx] = c.steps[a.ring] + (active ? 1 : 0);
-  if (!a.dt) c.qbits[nn] = 0ull;
+  if (!a.dt) qbits_clear(c, nn);
   // an inactive step copies its input, so its output keeps the input's flag;
   // an active step's CFL epilogue sets slot nx itself (cleared a step ago)
   if (!active) c.flags[nx] = c.flags[a.ring];
@@ -233,7 +250,7 @@ __device__ __forceinline__ void cfl_commit(const Args& a, int m, double qmax, bo
   // ignores it), so flag separately
   if (bad) atomicOr(&a.ctl[m].flags[slot], 1);
   if (threadIdx.x == 0 && v > 0.0)
-    atomicMax(&a.ctl[m].qbits[slot], (unsigned long long)__double_as_longlong(v));
+    atomicMax(&a.ctl[m].qbits[slot][blockIdx.x & (kQSub - 1)], (unsigned long long)__double_as_longlong(v));
 }
 
 // Tile geometry handed to the LDS kernels (computed on the host).
@@ -311,7 +328,7 @@ static __global__ void k_ctl_init(Ctl* ctl, const double* t0, int nmeshes, int r
     const double t_old = c.t[ring];
     const long long st_old = c.steps[ring];
     for (int s = 0; s < 3; ++s) {
-      c.qbits[s] = 0ull;
+      qbits_clear(c, s);
       c.t[s] = 0.0;
       c.steps[s] = 0;
       c.flags[s] = 0;
@@ -337,7 +354,7 @@ static __global__ void k_advance_init(Ctl* ctl, Params* prm, Params p, InlineTim
   if (m < nmeshes) {
     Ctl& c = ctl[m];
     for (int s = 0; s < 3; ++s) {
-      c.qbits[s] = 0ull;
+      qbits_clear(c, s);
       c.t[s] = 0.0;
       c.steps[s] = 0;
       c.flags[s] = 0;
@@ -358,7 +375,7 @@ __device__ __forceinline__ int find_mesh_chunk(const MeshDev* ms, int nm, int ch
   return lo;
 }
 
-// CFL maximum of the current state into qbits[ring]; one block of 256
+// CFL maximum of the current state into the sub-slots of qbits[ring]; one block of 256
 // threads per chunk of kChunk cells in storage order.  A full chunk is read
 // with 16-byte loads (4 FP32 or 2 FP64 cells per load and field), all of a
 // thread's loads issued before its arithmetic; a mesh's last, partial chunk

@@ -117,7 +117,7 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   double t = c.t[a.ring];
   long long steps = c.steps[a.ring];
   const long long steps0 = steps;
-  double qmax = explicit_dt ? 0.0 : __longlong_as_double((long long)c.qbits[a.ring]);
+  double qmax = explicit_dt ? 0.0 : __longlong_as_double((long long)qbits_max(c, a.ring));
   const double t_end = explicit_dt ? 0.0 : a.prm->t_end;
   const long long max_steps = explicit_dt ? 1 : a.prm->max_steps;
   const double cfl = explicit_dt ? 0.0 : a.prm->cfl;
@@ -179,8 +179,9 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     c.flags[nx] = bad ? 1 : 0;
     c.flags[nn] = 0;
     if (!explicit_dt) {
-      c.qbits[nx] = (unsigned long long)__double_as_longlong(qmax);
-      c.qbits[nn] = 0ull;
+      qbits_clear(c, nx);
+      c.qbits[nx][0] = (unsigned long long)__double_as_longlong(qmax);
+      qbits_clear(c, nn);
     }
   }
 }

@@ -914,7 +914,7 @@ int32_t paraiso_cfl_dt(paraiso_ctx* c, double cfl, double* dt_out) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int m = 0; m < c->count; ++m) {
     if (h[m].flags[c->ring]) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": non-physical state");
-    uint64_t bits = h[m].qbits[c->ring];
+    uint64_t bits = qbits_max(h[m], c->ring);
     double q;
     std::memcpy(&q, &bits, sizeof(q));
     if (!(q > 0.0)) return fail(PARAISO_ERR_NONFINITE, "mesh " + std::to_string(m) + ": no signal speed");

@@ -31,7 +31,7 @@ constexpr size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr size_t kTableBytes = round256(sizeof(MeshDev) * PARAISO_STATIC_MESHES);
 constexpr size_t kCtlBytes = round256(sizeof(Ctl) * PARAISO_STATIC_MESHES);
 constexpr size_t kScratchBytes = kTableBytes + kCtlBytes;
-static_assert(kScratchBytes <= 32 * 1024, "static scratch: at most 32 KiB per device");
+static_assert(kScratchBytes <= 48 * 1024, "static scratch: at most 48 KiB per device");
 
 // The mesh table (MeshDev[PARAISO_STATIC_MESHES]) followed by the control
 // blocks (Ctl[PARAISO_STATIC_MESHES]); each device holds its own copy.
@@ -180,7 +180,8 @@ extern "C" int32_t paraiso_cfl_dt_static(const paraiso_mesh* meshes, int32_t cou
   if (e != hipSuccess) return hip_fail(e);
   for (int m = 0; m < count; ++m) {
     double q;
-    std::memcpy(&q, &h_ctl[m].qbits[0], sizeof(q));
+    const unsigned long long bits = qbits_max(h_ctl[m], 0);
+    std::memcpy(&q, &bits, sizeof(q));
     if (h_ctl[m].flags[0] || !(q > 0.0)) return fail(PARAISO_ERR_NONFINITE, "cfl_dt_static: non-physical state");
     dt_out[m] = cfl / q;
   }
