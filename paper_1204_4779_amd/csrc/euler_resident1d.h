@@ -37,15 +37,10 @@ __device__ __forceinline__ void resident_face(const MeshDev& M, const Gas<T>& g,
   hllc<T, 1, 0>(vl, vr, fl, g);
 }
 
-// One stage over the resident mesh.  No barrier at the end: the next stage
-// first writes sV, which every thread has finished reading at the barrier
-// after the flux phase, and writes sF only after its own first barrier.
+// Primitives of this thread's cells into LDS (the first phase of a stage).
 template <typename T>
-__device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g, int n, T coef,
-                                               const T (*uin)[3], const T (*ubase)[3], T (*uout)[3], T* sV,
-                                               T* sF) {
+__device__ __forceinline__ void resident_prims(int n, const Gas<T>& g, const T (*uin)[3], T* sV) {
   const int tid = threadIdx.x;
-  // primitives of this thread's cells into LDS
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
     const int i = tid + r * kResidentThreads;
@@ -56,11 +51,20 @@ __device__ __forceinline__ void resident_stage(const MeshDev& M, const Gas<T>& g
       for (int q = 0; q < 3; ++q) sV[q * n + i] = v[q];
     }
   }
-  __syncthreads();
-  // faces f = 0..n: thread t takes t, t + kResidentThreads, ...  A wave with
-  // a lane that holds two faces in one round evaluates both in one pass (two
-  // independent chains), so the (n + 1)-th face of a mesh of a multiple of
-  // kResidentThreads cells does not cost a round of its own.
+}
+
+// The rest of a stage, after the barrier that publishes sV: faces f = 0..n
+// (thread t takes t, t + kResidentThreads, ...; a wave with a lane that
+// holds two faces in one round evaluates both in one pass, two independent
+// chains, so the (n + 1)-th face of a mesh of a multiple of kResidentThreads
+// cells does not cost a round of its own), one barrier, the update.  No
+// barrier at the end: the next stage first writes sV, which every thread has
+// finished reading at the barrier after the flux phase, and writes sF only
+// after its own first barrier.
+template <typename T>
+__device__ __forceinline__ void resident_flux_update(const MeshDev& M, const Gas<T>& g, int n, T coef,
+                                                     const T (*ubase)[3], T (*uout)[3], const T* sV, T* sF) {
+  const int tid = threadIdx.x;
   for (int f0 = tid; f0 <= n; f0 += 2 * kResidentThreads) {
     const int f1 = f0 + kResidentThreads;
     T fa[3];
@@ -123,26 +127,16 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   const double cfl = explicit_dt ? 0.0 : a.prm->cfl;
   // a non-physical input (flagged by the CFL reduction before the launch) is not stepped
   bool bad = !explicit_dt && c.flags[a.ring] != 0;
-  for (;;) {
-    double dt;
-    if (explicit_dt) {
-      if (steps > steps0) break;
-      dt = a.dt[m];
-    } else {
-      if (!(t < t_end) || steps >= max_steps || bad) break;
-      dt = cfl / qmax;
-      if (dt > t_end - t) dt = t_end - t;
-    }
-    const T c1 = (T)((0.5 * dt) * M.inv_dx[0]);
-    const T c2 = (T)(dt * M.inv_dx[0]);
-    resident_stage<T>(M, g, n, c1, u, u, u1, sV, sF);
-    resident_stage<T>(M, g, n, c2, u1, u, u, sV, sF);
-    t += dt;
-    ++steps;
-    if (!explicit_dt) {
-      // CFL maximum of the new state, a non-physical cell counted as +inf:
-      // each wave reduces its lanes, one barrier, and every thread folds the
-      // waves' maxima itself (s_red is next written after two more barriers)
+  // Each step opens with stage 1's primitives going to LDS; in an advance the
+  // same phase reduces the CFL maximum of that state (from the second step
+  // on: the first takes the reduction made before the launch), each wave
+  // into s_red, so the barrier that publishes sV publishes the wave maxima
+  // too, and every thread then folds them itself.  s_red is next written
+  // three barriers later.  A non-physical cell counts as +inf.
+  for (bool first = true;; first = false) {
+    resident_prims<T>(n, g, u, sV);
+    const bool reduce = !explicit_dt && !first;
+    if (reduce) {
       double q = 0.0;
       bool b = false;
 #pragma unroll
@@ -156,12 +150,31 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
       if ((tid & 63) == 0) s_red[tid >> 6] = v;
-      __syncthreads();
-      v = s_red[0];
+    }
+    __syncthreads();
+    if (reduce) {
+      double v = s_red[0];
       for (int k = 1; k < kResidentThreads / 64; ++k) v = fmax(v, s_red[k]);
       bad = !(v < __builtin_huge_val());
       qmax = v;
     }
+    double dt;
+    if (explicit_dt) {
+      if (steps > steps0) break;
+      dt = a.dt[m];
+    } else {
+      if (!(t < t_end) || steps >= max_steps || bad) break;
+      dt = cfl / qmax;
+      if (dt > t_end - t) dt = t_end - t;
+    }
+    const T c1 = (T)((0.5 * dt) * M.inv_dx[0]);
+    const T c2 = (T)(dt * M.inv_dx[0]);
+    resident_flux_update<T>(M, g, n, c1, u, u1, sV, sF);
+    resident_prims<T>(n, g, u1, sV);
+    __syncthreads();
+    resident_flux_update<T>(M, g, n, c2, u, u, sV, sF);
+    t += dt;
+    ++steps;
   }
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
