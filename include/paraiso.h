@@ -125,7 +125,9 @@ typedef struct paraiso_mesh {
  *                caps registers per lane at 168, 128 or 100;
  *   threads      workgroup size, a multiple of 64 in [64, 512], or 0 for
  *                the default of the chosen kernel (the 3D register march:
- *                64 * tile[1], up to 768 when fused);
+ *                64 * tile[1], up to 768 when fused; the resident kernel:
+ *                512 or 1024, each thread holding up to 4 cells, and 0
+ *                picks 512 for meshes of at most 2048 cells, else 1024);
  *   manifest     what an LDS tile (lds = 1) keeps between the phases of an
  *                axis, the paper's Manifest/Delayed choice for the results
  *                of the interpolation and of the Riemann solver (section

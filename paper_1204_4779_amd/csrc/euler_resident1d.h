@@ -18,9 +18,14 @@
 
 namespace paraiso {
 
-constexpr int kResidentThreads = 1024;
+// Workgroups of 512 or 1024 threads, each thread holding up to
+// kResidentPerThread cells: a mesh of up to 2048 cells runs on 512 threads
+// (Sod 1024 FP64: 4.61-4.65 ms to t = 0.2 against 4.94 ms on 1024 and
+// 6.5 ms on 256, whose waves lack the latency cover), larger ones on 1024.
+constexpr int kResidentThreads = 1024;  // the largest workgroup
 constexpr int kResidentPerThread = 4;
 constexpr int kResidentCells = kResidentThreads * kResidentPerThread;
+constexpr int resident_threads_for(int64_t cells) { return cells <= 512 * kResidentPerThread ? 512 : 1024; }
 
 // HLLC flux of face f (between cells f-1 and f) from the primitives in LDS.
 template <typename T>
@@ -38,12 +43,12 @@ __device__ __forceinline__ void resident_face(const MeshDev& M, const Gas<T>& g,
 }
 
 // Primitives of this thread's cells into LDS (the first phase of a stage).
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void resident_prims(int n, const Gas<T>& g, const T (*uin)[3], T* sV) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
-    const int i = tid + r * kResidentThreads;
+    const int i = tid + r * NT;
     if (i < n) {
       T v[3];
       prim_of_cons<T, 1>(uin[r], v, g);
@@ -54,19 +59,19 @@ __device__ __forceinline__ void resident_prims(int n, const Gas<T>& g, const T (
 }
 
 // The rest of a stage, after the barrier that publishes sV: faces f = 0..n
-// (thread t takes t, t + kResidentThreads, ...; a wave with a lane that
-// holds two faces in one round evaluates both in one pass, two independent
-// chains, so the (n + 1)-th face of a mesh of a multiple of kResidentThreads
-// cells does not cost a round of its own), one barrier, the update.  No
+// (thread t takes t, t + NT, ...; a wave with a lane that holds two faces in
+// one round evaluates both in one pass, two independent chains, so the
+// (n + 1)-th face of a mesh of a multiple of NT cells does not cost a round
+// of its own), one barrier, the update.  No
 // barrier at the end: the next stage first writes sV, which every thread has
 // finished reading at the barrier after the flux phase, and writes sF only
 // after its own first barrier.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void resident_flux_update(const MeshDev& M, const Gas<T>& g, int n, T coef,
                                                      const T (*ubase)[3], T (*uout)[3], const T* sV, T* sF) {
   const int tid = threadIdx.x;
-  for (int f0 = tid; f0 <= n; f0 += 2 * kResidentThreads) {
-    const int f1 = f0 + kResidentThreads;
+  for (int f0 = tid; f0 <= n; f0 += 2 * NT) {
+    const int f1 = f0 + NT;
     T fa[3];
     if (__builtin_amdgcn_ballot_w64(f1 <= n)) {
       T fb[3];
@@ -85,7 +90,7 @@ __device__ __forceinline__ void resident_flux_update(const MeshDev& M, const Gas
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
-    const int i = tid + r * kResidentThreads;
+    const int i = tid + r * NT;
     if (i < n) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -96,10 +101,10 @@ __device__ __forceinline__ void resident_flux_update(const MeshDev& M, const Gas
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom) {
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_resident1d(Args a, LdsGeom) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double s_red[kResidentThreads / 64];
+  __shared__ double s_red[NT / 64];
   const int m = blockIdx.x;
   const MeshDev& M = a.meshes[m];
   const int n = M.n[0];
@@ -112,7 +117,7 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   T u[kResidentPerThread][3], u1[kResidentPerThread][3];
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
-    const int i = tid + r * kResidentThreads;
+    const int i = tid + r * NT;
 #pragma unroll
     for (int q = 0; q < 3; ++q) u[r][q] = i < n ? U0.f[q][i] : T(1);
   }
@@ -134,14 +139,14 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
   // too, and every thread then folds them itself.  s_red is next written
   // three barriers later.  A non-physical cell counts as +inf.
   for (bool first = true;; first = false) {
-    resident_prims<T>(n, g, u, sV);
+    resident_prims<T, NT>(n, g, u, sV);
     const bool reduce = !explicit_dt && !first;
     if (reduce) {
       double q = 0.0;
       bool b = false;
 #pragma unroll
       for (int r = 0; r < kResidentPerThread; ++r) {
-        const int i = tid + r * kResidentThreads;
+        const int i = tid + r * NT;
         if (i < n) {
           cfl_fold(cfl_q<T, 1>(u[r], M.inv_dx, M.gamma), q, b);
         }
@@ -154,7 +159,7 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     __syncthreads();
     if (reduce) {
       double v = s_red[0];
-      for (int k = 1; k < kResidentThreads / 64; ++k) v = fmax(v, s_red[k]);
+      for (int k = 1; k < NT / 64; ++k) v = fmax(v, s_red[k]);
       bad = !(v < __builtin_huge_val());
       qmax = v;
     }
@@ -169,16 +174,16 @@ __global__ void __launch_bounds__(kResidentThreads) k_resident1d(Args a, LdsGeom
     }
     const T c1 = (T)((0.5 * dt) * M.inv_dx[0]);
     const T c2 = (T)(dt * M.inv_dx[0]);
-    resident_flux_update<T>(M, g, n, c1, u, u1, sV, sF);
-    resident_prims<T>(n, g, u1, sV);
+    resident_flux_update<T, NT>(M, g, n, c1, u, u1, sV, sF);
+    resident_prims<T, NT>(n, g, u1, sV);
     __syncthreads();
-    resident_flux_update<T>(M, g, n, c2, u, u, sV, sF);
+    resident_flux_update<T, NT>(M, g, n, c2, u, u, sV, sF);
     t += dt;
     ++steps;
   }
 #pragma unroll
   for (int r = 0; r < kResidentPerThread; ++r) {
-    const int i = tid + r * kResidentThreads;
+    const int i = tid + r * NT;
     if (i < n) {
 #pragma unroll
       for (int q = 0; q < 3; ++q) Uout.f[q][i] = u[r][q];

@@ -26,7 +26,7 @@ const KernelTable* table_f32_1() {
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
-      (const void*)k_resident1d<float>,
+      {(const void*)k_resident1d<float, 512>, (const void*)k_resident1d<float, 1024>},
       (const void*)k_cfl<float, 1>,
       (const void*)k_totals_partial<float, 1>,
       (const void*)k_totals_final<1>,

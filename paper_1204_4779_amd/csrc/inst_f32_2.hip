@@ -29,7 +29,7 @@ const KernelTable* table_f32_2() {
       {(const void*)k_march2d<float, 0, false, true>, (const void*)k_march2d<float, 3, false, true>,
        (const void*)k_march2d<float, 4, false, true>, (const void*)k_march2d<float, 5, false, true>},
       {nullptr, nullptr, nullptr, nullptr},
-      nullptr,
+      {nullptr, nullptr},
       (const void*)k_cfl<float, 2>,
       (const void*)k_totals_partial<float, 2>,
       (const void*)k_totals_final<2>,

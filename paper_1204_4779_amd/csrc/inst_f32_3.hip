@@ -27,7 +27,7 @@ const KernelTable* table_f32_3() {
       {nullptr, nullptr, nullptr, nullptr},
       {(const void*)k_march3d<float, 0>, (const void*)k_march3d<float, 3>, (const void*)k_march3d<float, 4>,
        (const void*)k_march3d<float, 5>},
-      nullptr,
+      {nullptr, nullptr},
       (const void*)k_cfl<float, 3>,
       (const void*)k_totals_partial<float, 3>,
       (const void*)k_totals_final<3>,

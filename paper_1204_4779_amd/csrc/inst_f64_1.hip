@@ -26,7 +26,7 @@ const KernelTable* table_f64_1() {
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
       {nullptr, nullptr, nullptr, nullptr},
-      (const void*)k_resident1d<double>,
+      {(const void*)k_resident1d<double, 512>, (const void*)k_resident1d<double, 1024>},
       (const void*)k_cfl<double, 1>,
       (const void*)k_totals_partial<double, 1>,
       (const void*)k_totals_final<1>,

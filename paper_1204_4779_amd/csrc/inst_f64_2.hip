@@ -29,7 +29,7 @@ const KernelTable* table_f64_2() {
       {(const void*)k_march2d<double, 0, false, true>, (const void*)k_march2d<double, 3, false, true>,
        (const void*)k_march2d<double, 4, false, true>, (const void*)k_march2d<double, 5, false, true>},
       {nullptr, nullptr, nullptr, nullptr},
-      nullptr,
+      {nullptr, nullptr},
       (const void*)k_cfl<double, 2>,
       (const void*)k_totals_partial<double, 2>,
       (const void*)k_totals_final<2>,

@@ -27,7 +27,7 @@ const KernelTable* table_f64_3() {
       {nullptr, nullptr, nullptr, nullptr},
       {(const void*)k_march3d<double, 0>, (const void*)k_march3d<double, 3>, (const void*)k_march3d<double, 4>,
        (const void*)k_march3d<double, 5>},
-      nullptr,
+      {nullptr, nullptr},
       (const void*)k_cfl<double, 3>,
       (const void*)k_totals_partial<double, 3>,
       (const void*)k_totals_final<3>,

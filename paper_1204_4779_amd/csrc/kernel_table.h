@@ -19,7 +19,7 @@ struct KernelTable {
   const void* march_stage[4];
   const void* march_stage_an[4];  // one stage with analytic ghost cells from the ghost arrays (2D)
   const void* march3d_stage[4];  // 3D register march, one stage (null for other dimensions)
-  const void* resident1d;        // whole-advance kernel of small 1D meshes (null otherwise)
+  const void* resident1d[2];     // whole-advance kernel of small 1D meshes, 512 / 1024 threads (null otherwise)
   const void* cfl;
   const void* totals_partial;
   const void* totals_final;

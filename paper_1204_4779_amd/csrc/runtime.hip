@@ -411,6 +411,12 @@ size_t march3d_fused_lds(int nw, int esize) {
   return (size_t)esize * 5 * 64 * (2 * (size_t)(nw + 4) + 2 * (size_t)nw + 3 * (size_t)(nw + 1) + 3 * (size_t)(nw - 3));
 }
 
+int64_t max_cells(const paraiso_mesh* meshes, int count) {
+  int64_t n = 1;
+  for (int m = 0; m < count; ++m) n = std::max<int64_t>(n, cells_of(meshes[m]));
+  return n;
+}
+
 int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string& why) {
   const int d = c->ndim;
   for (int a = 0; a < 3; ++a) {
@@ -426,9 +432,13 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
   if (v.lds < 0 || v.lds > 3) return why = "lds must be 0, 1, 2 or 3", PARAISO_ERR_UNSUPPORTED;
   if (v.lds == 3) {
     if (d != 1) return why = "resident kernel (lds = 3) exists for 1D meshes only", PARAISO_ERR_UNSUPPORTED;
+    if (v.threads != 0 && v.threads != 512 && v.threads != 1024)
+      return why = "resident kernel: threads must be 0 (chosen from the largest mesh), 512 or 1024",
+             PARAISO_ERR_UNSUPPORTED;
+    const int cap = v.threads ? kResidentPerThread * v.threads : kResidentCells;
     for (const auto& m : c->meshes) {
-      if (m.n[0] > kResidentCells)
-        return why = "resident kernel: at most " + std::to_string(kResidentCells) + " cells per mesh",
+      if (m.n[0] > cap)
+        return why = "resident kernel: at most " + std::to_string(cap) + " cells per mesh with this workgroup",
                PARAISO_ERR_UNSUPPORTED;
       if ((size_t)c->esize * (6 * (size_t)m.n[0] + 3) + 256 > (size_t)c->max_lds)
         return why = "resident kernel: mesh does not fit in LDS", PARAISO_ERR_UNSUPPORTED;
@@ -481,10 +491,8 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
     return why = "waves_per_eu must be 0, 3, 4 or 5", PARAISO_ERR_UNSUPPORTED;
   // (the fused 3D march runs one wave per stage-1 row, up to 768 threads; its own check below)
   const bool fused3d = v.lds == 2 && c->ndim == 3 && v.fuse;
-  // the resident kernel always runs one workgroup of kResidentThreads per
-  // mesh, the count paraiso_get_variant reports; it ignores other counts
-  const bool resident_count = v.lds == 3 && v.threads == kResidentThreads;
-  if (v.threads != 0 && !fused3d && !resident_count && (v.threads < 64 || v.threads > 512 || v.threads % 64))
+  // (the resident kernel's counts are checked above)
+  if (v.threads != 0 && !fused3d && v.lds != 3 && (v.threads < 64 || v.threads > 512 || v.threads % 64))
     return why = "threads must be 0 or a multiple of 64 in [64, 512]", PARAISO_ERR_UNSUPPORTED;
   const int64_t tc = (int64_t)v.tile[0] * v.tile[1] * v.tile[2];
   if (tc > (1 << 22)) return why = "tile has more than 2^22 cells", PARAISO_ERR_UNSUPPORTED;
@@ -497,7 +505,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   int rc = validate_variant(c, v, why);
   if (rc) return fail(rc, "variant: " + why);
   const int d = c->ndim, nf = d + 2;
-  const int threads = v.lds == 3 ? kResidentThreads
+  const int threads = v.lds == 3 ? (v.threads ? v.threads : resident_threads_for(max_cells(c->meshes.data(), c->count)))
                       : (v.lds == 2 && d == 3) ? 64 * v.tile[1] : (v.threads ? v.threads : 256);
   // tile of one work item: the variant's tile, or for the register march
   // (64 - 2H) columns by rows-per-wave times waves-per-block
@@ -585,7 +593,7 @@ int apply_variant(paraiso_ctx* c, const paraiso_variant& vin) {
   // periodic wrap; nothing else to check
   const int ws = waves_slot(v.waves_per_eu);
   Launch L;
-  if (v.lds == 3) L.fn = c->tab->resident1d;
+  if (v.lds == 3) L.fn = c->tab->resident1d[threads == 512 ? 0 : 1];
   else if (v.lds == 2 && d == 3) L.fn = v.fuse ? c->tab->march3d_fused[ws] : c->tab->march3d_stage[ws];
   else if (v.lds == 2)
     L.fn = v.fuse ? c->tab->march_fused[ws]
@@ -720,7 +728,7 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
       v->lds = 3;
       v->fuse = 1;
       v->tile[0] = (int32_t)nmax;
-      v->threads = kResidentThreads;
+      v->threads = resident_threads_for(nmax);
     }
   } else if (!march_offsets_fit(meshes, count)) {
     // rows or planes beyond the march kernels' 32-bit offsets: LDS tiles

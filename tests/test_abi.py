@@ -120,6 +120,9 @@ def test_default_variant(lib):
     assert pb.paraiso_default_variant([_mesh(1, (4097, 1, 1))]).lds == 1
     assert pb.paraiso_default_variant([_mesh(1, (3407, 1, 1), pb.F64)]).lds == 3
     assert pb.paraiso_default_variant([_mesh(1, (3408, 1, 1), pb.F64)]).lds == 1
+    assert pb.paraiso_default_variant([_mesh(1, (4096, 1, 1))]).threads == 1024
+    assert pb.paraiso_default_variant([_mesh(1, (2048, 1, 1))]).threads == 512
+    assert pb.paraiso_default_variant([_mesh(1, (2049, 1, 1))]).threads == 1024
     v1 = pb.paraiso_default_variant([_mesh(1, (100, 1, 1)), _mesh(1, (1000, 1, 1))])
     assert (v1.lds, v1.tile[0], v1.persistent) == (3, 1000, 0)
     # the march kernels take 32-bit byte offsets within a row (2D) / plane (3D)

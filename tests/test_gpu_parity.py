@@ -501,7 +501,7 @@ RESIDENT_MAX = {"f32": 4096, "f64": 3407}
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("bc", [0, 1])
-@pytest.mark.parametrize("n", [1, 3, 203, 1024, "max"])
+@pytest.mark.parametrize("n", [1, 3, 203, 1024, 2048, 2049, "max"])
 def test_resident_1d_step_matches_oracle(dtype, bc, n):
     n = RESIDENT_MAX[dtype] if n == "max" else n
     pr = inputs.random_state(1, (n,), seed=500 + n + bc, rough=True, bc=(bc,))
@@ -510,8 +510,28 @@ def test_resident_1d_step_matches_oracle(dtype, bc, n):
     dt = oracle.cfl_dt(m, U0, 0.5)
     ref = oracle.step(m, U0, dt)
     s = gpu_solver(spec_of(pr), dtype, dict(tile=(n,), lds=3, fuse=1), pr.U)
+    # the workgroup follows the mesh: 512 threads up to 2048 cells, else 1024
+    assert s.variant()["threads"] == (512 if n <= 2048 else 1024)
     s.step(dt)
     assert rel_err(gpu_state(s), ref) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 203, 1024, 2048])
+def test_resident_1d_workgroup_sizes_agree(dtype, n):
+    # 512 and 1024 threads hold the same cells in different places: one
+    # advance of 20 device-dt steps gives the same bits and the same time
+    print(f"case resident workgroups {dtype} n={n}", flush=True)
+    pr = inputs.random_state(1, (n,), seed=900 + n, bc=(1,))
+    out = []
+    for threads in (512, 1024):
+        s = gpu_solver(spec_of(pr), dtype, dict(tile=(n,), lds=3, fuse=1, threads=threads), pr.U)
+        assert s.variant()["threads"] == threads
+        t, k = s.advance(1e9, 0.5, max_steps=20)
+        out.append((gpu_state(s), t, k))
+        s.close()
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1:] == out[1][1:] and out[0][2] == [20]
 
 
 def test_resident_1d_sod_advance_and_batch():
@@ -553,3 +573,12 @@ def test_resident_1d_rejects_large_and_2d():
     s2 = gpu_solver(spec_of(pr2), "f64", None, pr2.U)
     with pytest.raises(pb.ParaisoError):
         s2.set_variant(dict(tile=(16, 16), lds=3, fuse=1))
+    # 512 threads hold at most 2048 cells; other workgroup sizes do not exist
+    pr3 = inputs.random_state(1, (2049,), seed=1)
+    s3 = gpu_solver(spec_of(pr3), "f64", None, pr3.U)
+    with pytest.raises(pb.ParaisoError):
+        s3.set_variant(dict(tile=(2049,), lds=3, fuse=1, threads=512))
+    s3.set_variant(dict(tile=(2049,), lds=3, fuse=1, threads=1024))
+    for bad in (256, 768):
+        with pytest.raises(pb.ParaisoError):
+            s3.set_variant(dict(tile=(2049,), lds=3, fuse=1, threads=bad))
