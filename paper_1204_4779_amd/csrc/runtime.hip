@@ -175,9 +175,25 @@ int validate_meshes(const paraiso_mesh* ms, int count) {
   return PARAISO_OK;
 }
 
-// Ghost arrays of a 2D mesh with an analytic axis (both stages, d+2 fields).
+// The analytic 2D register march addresses its ghost arrays (both stages,
+// 4 fields, ghost_stride cells each) with 32-bit offsets: meshes whose
+// arrays pass that (n[0] + n[1] near 2^26 or more) take the LDS tiles, which
+// evaluate the exact solution in place and keep no ghost arrays.
+bool ghosts_fit(const paraiso_mesh& m) {
+  const int64_t stride = 4 * ((int64_t)m.n[1] + 4) + 4 * ((int64_t)m.n[0] + 4);
+  return 8 * stride < (int64_t(1) << 31);
+}
+
+bool all_ghosts_fit(const paraiso_mesh* ms, int count) {
+  for (int i = 0; i < count; ++i)
+    if (ms[i].ndim == 2 && has_analytic(ms[i]) && !ghosts_fit(ms[i])) return false;
+  return true;
+}
+
+// Ghost arrays of a 2D mesh with an analytic axis (both stages, d+2 fields),
+// for the register march; none where that march cannot run.
 size_t ghost_bytes(const paraiso_mesh& m) {
-  if (m.ndim != 2 || !has_analytic(m)) return 0;
+  if (m.ndim != 2 || !has_analytic(m) || !ghosts_fit(m)) return 0;
   const size_t esize = m.dtype == PARAISO_F32 ? 4 : 8;
   return align256(2 * 4 * (size_t)ghost_stride((int)m.n[0], (int)m.n[1]) * esize);
 }
@@ -449,6 +465,8 @@ int validate_variant(const paraiso_ctx* c, const paraiso_variant& v, std::string
     if (v.tile[0] != 64) return why = "register march: tile[0] must be 64 (one wave of columns)", PARAISO_ERR_UNSUPPORTED;
     if (!march_offsets_fit(c->meshes.data(), c->count))
       return why = "register march: a row (2D) or plane (3D) spans 4 GiB or more", PARAISO_ERR_UNSUPPORTED;
+    if (!all_ghosts_fit(c->meshes.data(), c->count))
+      return why = "register march: the ghost arrays of an analytic mesh pass 32-bit offsets", PARAISO_ERR_UNSUPPORTED;
     if (d == 2) {
       if (v.fuse)
         for (const auto& m : c->meshes)
@@ -708,7 +726,7 @@ void default_variant(const paraiso_mesh* meshes, int count, paraiso_variant* v) 
   lds_variant(d, v);
   if (any_analytic(meshes, count)) {
     v->fuse = 0;  // ghosts at each stage's own time
-    if (d == 2 && !first_order(meshes[0]) && march_offsets_fit(meshes, count)) {
+    if (d == 2 && !first_order(meshes[0]) && march_offsets_fit(meshes, count) && all_ghosts_fit(meshes, count)) {
       // the one-stage register march with ghost arrays
       v->lds = 2;
       v->tile[0] = 64;

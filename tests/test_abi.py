@@ -136,6 +136,15 @@ def test_default_variant(lib):
     for d, n in ((1, (64, 1, 1)), (2, (8, 8, 1)), (3, (4, 4, 4))):
         v = pb.paraiso_default_variant([_mesh(d, n, bc=(pb.ANALYTIC, 0, 0))])
         assert (v.lds, v.fuse) == ((2, 0) if d == 2 else (1, 0)), d
+    # the analytic march's ghost arrays take 32-bit offsets: meshes past them get
+    # LDS tiles (exact solution in place) and no ghost arrays in the workspace
+    fits = _mesh(2, ((1 << 26) - 100, 2, 1), bc=(pb.ANALYTIC, 0, 0))
+    big = _mesh(2, (1 << 26, 2, 1), bc=(pb.ANALYTIC, 0, 0))
+    assert pb.paraiso_default_variant([fits]).lds == 2
+    assert pb.paraiso_default_variant([big]).lds == 1
+    ghosts = 2 * 4 * (4 * (2 + 4) + 4 * ((1 << 26) - 100 + 4)) * 4
+    assert pb.paraiso_workspace_bytes([fits]) > ghosts
+    assert pb.paraiso_workspace_bytes([big]) < pb.paraiso_workspace_bytes([fits])
     v = pb.paraiso_default_variant([_mesh(), _mesh(bc=(0, pb.ANALYTIC, 0))])
     assert (v.lds, v.fuse, v.persistent, tuple(v.tile)) == (2, 0, 0, (64, 8, 1))
     v = pb.paraiso_default_variant([_mesh(dtype=pb.F64, bc=(pb.ANALYTIC,) * 3)])
