@@ -250,7 +250,7 @@ __device__ __forceinline__ void cfl_commit(const Args& a, int m, double qmax, bo
   // ignores it), so flag separately
   if (bad) atomicOr(&a.ctl[m].flags[slot], 1);
   if (threadIdx.x == 0 && v > 0.0)
-    atomicMax(&a.ctl[m].qbits[slot][blockIdx.x & (kQSub - 1)], (unsigned long long)__double_as_longlong(v));
+    atomicMax(&a.ctl[m].qbits[slot][blockIdx.x % kQSub], (unsigned long long)__double_as_longlong(v));
 }
 
 // Tile geometry handed to the LDS kernels (computed on the host).
